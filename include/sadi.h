@@ -1,0 +1,144 @@
+/*
+ * sadi.h -- C ABI of the MI355X (gfx950) implementation of the splitting-ADI
+ * (S-ADI) time stepping of Sun & Sun, "Splitting ADI scheme for fractional
+ * Laplacian wave equations" (arXiv 2312.06206).
+ *
+ * Problem (section "Introduction"): d^2u/dt^2 = -kappa (-Delta)^{alpha/2} u + g(u) on
+ * Omega = (a,b)^2, u = 0 outside Omega, u(0) = phi1, u_t(0) = phi2, 1 < alpha < 2.
+ * Grid (section "Construction of S-ADI scheme"): N interior nodes per direction,
+ * h = (b-a)/(N+1), x_i = a + i h; tau is the time step.
+ *
+ * One step (section "Fast implementation based on GS formula", delta form):
+ *   (1 + tau^2 kappa/2 delta_x)(1 + tau^2 kappa/2 delta_y) Uhat = B,
+ *   B = -tau^2 kappa L_h u^n + tau^2 g(u^n)                        (n >= 1)
+ *   B = tau phi2 - tau^2/2 kappa L_h u^0 + tau^2/2 g(u^0)          (n = 0)
+ *   u^{n+1} = 2 u^n - u^{n-1} + Uhat  (n >= 1),   u^1 = u^0 + Uhat  (n = 0)
+ * with L_h applied by a block-circulant embedding and 2D FFT, and the two line
+ * sweeps H^-1 (H = I + kappa tau^2/(2 h^alpha) T(a_0..a_{N-1})) by the
+ * Gohberg-Semencul formula (Proposition 1, Algorithm 1).
+ *
+ * Conventions for every grid array argument:
+ *   - DEVICE pointer to float64, owned by the caller, N*N elements, contiguous;
+ *   - element (x_i, y_j), 1 <= i,j <= N, is stored at index (j-1)*N + (i-1)
+ *     (x fastest: the paper's column-stacking vec(U));
+ *   - arrays must not overlap unless an entry point says so.
+ * Calls after setup are asynchronous on the context's stream (default: the null
+ * stream), allocate nothing and do not synchronise; device faults surface as
+ * SADI_E_DEVICE at a later call or synchronisation.  A context is not
+ * thread-safe; any number of contexts may coexist.  The library never aborts:
+ * every failure is a status plus a message from sadi_last_error().
+ *
+ * Supported sizes: N + 1 a power of two with 16 <= N + 1 <= 4096.
+ */
+#ifndef SADI_H
+#define SADI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sadi_ctx sadi_ctx;
+
+typedef enum {
+  SADI_OK = 0,
+  SADI_E_INVALID = -1,     /* bad argument (range, NULL, size) */
+  SADI_E_NOMEM = -2,       /* device or host allocation failed */
+  SADI_E_DEVICE = -3,      /* HIP runtime error (launch, copy, earlier async fault) */
+  SADI_E_UNSUPPORTED = -4, /* valid problem this build does not handle (e.g. N+1 not a power of two) */
+  SADI_E_STATE = -5        /* NULL or destroyed context */
+} sadi_status;
+
+/* Nonlinearity g(u). */
+typedef enum {
+  SADI_G_ZERO = 0,
+  SADI_G_NEG_SIN = 1,    /* -sin u   (sine-Gordon, the paper's first example) */
+  SADI_G_NEG_CUBE = 2,   /* -u^3     (Klein-Gordon, the paper's second example) */
+  SADI_G_NEG_LINEAR = 3  /* -m u     (m = g_param) */
+} sadi_g_kind;
+
+/* Arithmetic of the Gohberg-Semencul line solves (state, right-hand side and
+ * BTTB product are always float64). */
+typedef enum {
+  SADI_FP64 = 0,         /* float64 transforms */
+  SADI_FP32_REFINE = 1,  /* float32 transforms + one float64 residual correction per line */
+  SADI_FP32 = 2          /* float32 transforms only (error about 1e-7 relative) */
+} sadi_precision;
+
+/* Create a context for (alpha, kappa, N, tau, Omega = (domain[0], domain[1])^2).
+ * Validates 1 < alpha < 2, kappa > 0, tau > 0, domain[1] > domain[0] (all finite).
+ * Computes on the host: the 1D coefficients a_k (closed form, section 2), the 2D
+ * coefficients a_ij of L_h (Fourier coefficients of the symbol), the generating
+ * vector H^-1 e_1 of the bordered line matrix and its circulant / skew-circulant
+ * eigenvalues (Proposition 1), and the eigenvalues of the block-circulant
+ * embedding of L_h; uploads them and allocates the device workspaces.  Uses the
+ * current HIP device.  Host-synchronous.  Defaults: g = -sin u, float64.
+ * domain: host pointer to 2 doubles.  *out receives the context (NULL on error). */
+sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const double* domain, sadi_ctx** out);
+
+/* Same, with caller-supplied coefficient tables instead of the computed ones
+ * (host pointers): a1 holds a_0..a_N (N+1 values), a2 holds a_ij for
+ * 0 <= i,j < N at a2[j*N + i].  alpha only enters through h^alpha here, and
+ * alpha = 2 is accepted (classical 3-point / 5-point operators). */
+sadi_status sadi_setup_with_coeffs(double alpha, double kappa, int n, double tau, const double* domain,
+                                   const double* a1, const double* a2, sadi_ctx** out);
+
+/* Select g and the line-solve arithmetic (takes effect at the next call). */
+sadi_status sadi_set_options(sadi_ctx* ctx, sadi_g_kind g, double g_param, sadi_precision prec);
+
+/* Run subsequent calls on this HIP stream (a hipStream_t, e.g. torch's current
+ * stream); NULL selects the null stream.  The stream must outlive its use. */
+sadi_status sadi_set_stream(sadi_ctx* ctx, void* hip_stream);
+
+/* Start-up step n = 0 (scheme (ADI scheme initial)): u1 <- u^1 from u^0 = phi1 and
+ * u_t(0) = phi2.  phi1, phi2, u1: device grid arrays; u1 must not alias phi1/phi2. */
+sadi_status sadi_first_step(sadi_ctx* ctx, const double* phi1, const double* phi2, double* u1);
+
+/* One step n >= 1 (scheme (ADI scheme)): on entry u_prev = u^{n-1}, u_cur = u^n;
+ * on exit u_prev = u^{n+1} (u_cur unchanged). */
+sadi_status sadi_step(sadi_ctx* ctx, double* u_prev, const double* u_cur);
+
+/* nsteps >= 0 steps n >= 1.  On entry (u_prev, u_cur) = (u^{n-1}, u^n); on exit
+ * (u_prev, u_cur) = (u^{n+nsteps-1}, u^{n+nsteps}).  Odd nsteps costs one extra
+ * exchange of the two arrays through a workspace. */
+sadi_status sadi_run(sadi_ctx* ctx, double* u_prev, double* u_cur, int nsteps);
+
+/* In place, lines[r*ld + i] <- (H^-1 v_r)_i for r < nlines, i < N, where v_r is
+ * line r and H = I + kappa tau^2/(2 h^alpha) T(a_0..a_{N-1}) (Proposition 1 /
+ * Algorithm 1).  lines: device float64 pointer; ld >= N. */
+sadi_status sadi_toeplitz_solve(sadi_ctx* ctx, double* lines, int nlines, int ld);
+
+/* out <- L_h u (the discrete fractional Laplacian, section 2), device grid arrays,
+ * no aliasing. */
+sadi_status sadi_apply_lh(sadi_ctx* ctx, const double* u, double* out);
+
+/* Sizes of the context: N, M = N+1, and device bytes held (any pointer may be NULL). */
+sadi_status sadi_get_info(const sadi_ctx* ctx, int* n, int* m, long long* device_bytes);
+
+/* Free the context and its device memory (synchronises its stream).  NULL is a no-op. */
+sadi_status sadi_destroy(sadi_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* sadi_last_error(void);
+
+/* ---- host-only helpers (no GPU needed) ------------------------------------
+ * The host setup mathematics, exposed for testing and for callers that want
+ * the tables.  All pointers are HOST pointers. */
+
+/* a_k, k = 0..count-1, of the 1D fractional centred difference (closed form of
+ * section 2, evaluated by its Gamma-ratio recurrence in extended precision). */
+sadi_status sadi_host_riesz_coeffs(double alpha, int count, double* out);
+
+/* a_ij, 0 <= i,j < n, of L_h (out[j*n + i]); Fourier coefficients of
+ * (4 sin^2(eta/2) + 4 sin^2(xi/2))^{alpha/2}, computed through the subordination
+ * integral s^beta = beta/Gamma(1-beta) int_0^inf (1 - e^{-ts}) t^{-1-beta} dt. */
+sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out);
+
+/* c = H_M^-1 e_1 of the bordered line matrix (M = n+1 unknowns, Levinson-Durbin in
+ * extended precision); out has n+1 entries. */
+sadi_status sadi_host_line_generator(double alpha, double kappa, int n, double tau, const double* domain,
+                                     double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SADI_H */

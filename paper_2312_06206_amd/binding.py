@@ -1,0 +1,212 @@
+"""ctypes binding of libsadi.so (argument marshalling only; all work runs in the library).
+
+Grid arrays are torch.float64 CUDA (HIP) tensors of shape (N, N), contiguous, indexed
+[j, i] = u(x_i, y_j) (x fastest, the layout of include/sadi.h).  Calls are enqueued on
+torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsadi.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sadi.h")
+
+SADI_OK = 0
+STATUS = {0: "SADI_OK", -1: "SADI_E_INVALID", -2: "SADI_E_NOMEM", -3: "SADI_E_DEVICE",
+          -4: "SADI_E_UNSUPPORTED", -5: "SADI_E_STATE"}
+G_KINDS = {"zero": 0, "neg_sin": 1, "neg_cube": 2, "neg_linear": 3}
+PRECISIONS = {"fp64": 0, "fp32_refine": 1, "fp32": 2}
+
+
+class SadiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree libsadi.so; fails loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_06206_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, VP = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    DP = P(ctypes.c_double)
+    sig = {
+        "sadi_setup": (I, [D, D, I, D, DP, P(VP)]),
+        "sadi_setup_with_coeffs": (I, [D, D, I, D, DP, DP, DP, P(VP)]),
+        "sadi_set_options": (I, [VP, I, D, I]),
+        "sadi_set_stream": (I, [VP, VP]),
+        "sadi_first_step": (I, [VP, VP, VP, VP]),
+        "sadi_step": (I, [VP, VP, VP]),
+        "sadi_run": (I, [VP, VP, VP, I]),
+        "sadi_toeplitz_solve": (I, [VP, VP, I, I]),
+        "sadi_apply_lh": (I, [VP, VP, VP]),
+        "sadi_get_info": (I, [VP, P(I), P(I), P(ctypes.c_longlong)]),
+        "sadi_destroy": (I, [VP]),
+        "sadi_last_error": (ctypes.c_char_p, []),
+        "sadi_host_riesz_coeffs": (I, [D, I, DP]),
+        "sadi_host_laplacian_coeffs": (I, [D, I, DP]),
+        "sadi_host_line_generator": (I, [D, D, I, D, DP, DP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SADI_OK:
+        msg = load_library().sadi_last_error().decode()
+        raise SadiError(status, msg)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---- host-only helpers -----------------------------------------------------------
+def host_riesz_coeffs(alpha: float, count: int) -> np.ndarray:
+    out = np.empty(count)
+    _check(load_library().sadi_host_riesz_coeffs(alpha, count, _dptr(out)))
+    return out
+
+
+def host_laplacian_coeffs(alpha: float, n: int) -> np.ndarray:
+    """a_ij as an (n, n) array indexed [i, j] (the table is symmetric)."""
+    out = np.empty((n, n))
+    _check(load_library().sadi_host_laplacian_coeffs(alpha, n, _dptr(out)))
+    return out
+
+
+def host_line_generator(alpha, kappa, n, tau, domain=(-1.0, 1.0)) -> np.ndarray:
+    out = np.empty(n + 1)
+    dom = np.asarray(domain, dtype=np.float64)
+    _check(load_library().sadi_host_line_generator(alpha, kappa, n, tau, _dptr(dom), _dptr(out)))
+    return out
+
+
+# ---- device solver ---------------------------------------------------------------
+def _grid_ptr(t, n: int) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 CUDA tensor")
+    if tuple(t.shape) != (n, n) or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous ({n}, {n}) tensor")
+    return t.data_ptr()
+
+
+class Solver:
+    """S-ADI stepping on one GPU through the C ABI (see include/sadi.h)."""
+
+    def __init__(self, alpha: float, kappa: float, n: int, tau: float, domain: Sequence[float] = (-1.0, 1.0),
+                 g: str = "neg_sin", g_param: float = 0.0, precision: str = "fp64",
+                 a1: Optional[np.ndarray] = None, a2: Optional[np.ndarray] = None):
+        lib = load_library()
+        self.n, self.alpha, self.kappa, self.tau = int(n), float(alpha), float(kappa), float(tau)
+        self.domain = (float(domain[0]), float(domain[1]))
+        dom = np.asarray(self.domain, dtype=np.float64)
+        ctx = ctypes.c_void_p()
+        if a1 is None and a2 is None:
+            _check(lib.sadi_setup(self.alpha, self.kappa, self.n, self.tau, _dptr(dom), ctypes.byref(ctx)))
+        else:
+            a1 = np.ascontiguousarray(a1, dtype=np.float64)
+            a2 = np.ascontiguousarray(np.asarray(a2, dtype=np.float64).T)  # [j*N + i] = a_ij
+            if a1.size < self.n + 1 or a2.shape != (self.n, self.n):
+                raise ValueError("coefficient tables have the wrong size")
+            _check(lib.sadi_setup_with_coeffs(self.alpha, self.kappa, self.n, self.tau, _dptr(dom),
+                                              _dptr(a1), _dptr(a2), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.set_options(g, g_param, precision)
+
+    # -- plumbing
+    def _bind_stream(self):
+        import torch
+        _check(load_library().sadi_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def set_options(self, g: str = "neg_sin", g_param: float = 0.0, precision: str = "fp64"):
+        _check(load_library().sadi_set_options(self._ctx, G_KINDS[g], float(g_param), PRECISIONS[precision]))
+        self.g, self.g_param, self.precision = g, g_param, precision
+
+    @property
+    def info(self):
+        n, m, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+        _check(load_library().sadi_get_info(self._ctx, ctypes.byref(n), ctypes.byref(m), ctypes.byref(b)))
+        return {"n": n.value, "m": m.value, "device_bytes": b.value}
+
+    # -- entry points
+    def first_step(self, phi1, phi2, out=None):
+        import torch
+        n = self.n
+        if out is None:
+            out = torch.empty((n, n), dtype=torch.float64, device=phi1.device)
+        self._bind_stream()
+        _check(load_library().sadi_first_step(self._ctx, ctypes.c_void_p(_grid_ptr(phi1, n)),
+                                              ctypes.c_void_p(_grid_ptr(phi2, n)),
+                                              ctypes.c_void_p(_grid_ptr(out, n))))
+        return out
+
+    def step(self, u_prev, u_cur):
+        """u_prev <- u^{n+1} (in place); returns u_prev."""
+        self._bind_stream()
+        _check(load_library().sadi_step(self._ctx, ctypes.c_void_p(_grid_ptr(u_prev, self.n)),
+                                        ctypes.c_void_p(_grid_ptr(u_cur, self.n))))
+        return u_prev
+
+    def run(self, u_prev, u_cur, nsteps: int):
+        """(u_prev, u_cur) <- (u^{n+k-1}, u^{n+k}) in place."""
+        self._bind_stream()
+        _check(load_library().sadi_run(self._ctx, ctypes.c_void_p(_grid_ptr(u_prev, self.n)),
+                                       ctypes.c_void_p(_grid_ptr(u_cur, self.n)), int(nsteps)))
+        return u_prev, u_cur
+
+    def toeplitz_solve(self, lines):
+        """In place H^-1 on every row of a float64 CUDA tensor of shape (nlines, >= N)."""
+        import torch
+        if not isinstance(lines, torch.Tensor) or lines.dtype != torch.float64 or not lines.is_cuda:
+            raise TypeError("expected a float64 CUDA tensor")
+        if lines.dim() != 2 or lines.stride(1) != 1 or lines.shape[1] < self.n:
+            raise ValueError("expected shape (nlines, >= N) with unit stride along lines")
+        self._bind_stream()
+        _check(load_library().sadi_toeplitz_solve(self._ctx, ctypes.c_void_p(lines.data_ptr()),
+                                                  int(lines.shape[0]), int(lines.stride(0))))
+        return lines
+
+    def apply_lh(self, u, out=None):
+        import torch
+        n = self.n
+        if out is None:
+            out = torch.empty((n, n), dtype=torch.float64, device=u.device)
+        self._bind_stream()
+        _check(load_library().sadi_apply_lh(self._ctx, ctypes.c_void_p(_grid_ptr(u, n)),
+                                            ctypes.c_void_p(_grid_ptr(out, n))))
+        return out
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _check(load_library().sadi_destroy(self._ctx))
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,429 @@
+// Device kernels of the S-ADI time step (FP64 path).
+//
+// Grid layout: an N x N grid function u(x_i, y_j) is stored with x fastest,
+// element (i, j) at u[j * ld + i] (row j = the x-line y = y_j).  M = N + 1 is a
+// power of two; P = 2M >= 2N - 1 is the size of the block-circulant embedding of
+// the BTTB operator L_h (section "Fast implementation based on GS formula":
+// L_h u by embedding in a block circulant with circulant blocks and 2D FFT).
+//
+// Kernels of one step (delta form H Uhat H = B of that section):
+//   rows_fwd   : rFFT_P of every zero-padded x-line          u -> S (N x (M+1) complex)
+//   cols_conv  : per x-frequency column, FFT_P over y, times the BCCB eigenvalues,
+//                inverse FFT_P, first N rows kept             S -> S
+//   rows_rhs_gs: inverse rFFT_P of every row -> (L_h u) h^alpha; B = sigma L u + gamma g(u)
+//                (+ tau phi2 in the start-up step); x-line solve H^-1 B -> X
+//   cols_gs    : y-line solve H^-1 on every column of X, then the leapfrog update
+//                u^{n+1} = 2u^n - u^{n-1} + Uhat (start-up: u^1 = u^0 + Uhat)
+// Line solves use the Gohberg-Semencul formula (Proposition 1 / Algorithm 1 of
+// that section) on the bordered system of size M = N + 1, whose first N unknowns
+// follow from a rank-one correction (Schur complement of the bordered matrix).
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace sadi {
+
+using V = double2;
+
+// ----------------------------------------------------------------------------------
+// XCD-aware block order for column kernels: consecutive dispatch slots go to the 8
+// XCDs round robin, so give the blocks of one XCD adjacent column groups (their row
+// segments then share L2 lines).
+__device__ __forceinline__ int xcd_group(int nblocks_used) {
+  const int per = (nblocks_used + 7) / 8;
+  const int b = blockIdx.x;
+  return (b % 8) * per + b / 8;
+}
+
+// ----------------------------------------------------------------------------------
+// Gohberg-Semencul solve on a line in canonical layout.  On entry slot m holds
+// v1[k] = v[k] + i v[M-1-k], k = t + T m (v the bordered right-hand side, v[M-1] = 0).
+// On exit slot m holds w[k] = (H_M^-1 [v;0])[k] minus the bordering correction,
+// i.e. (H_N^-1 v)[k] for k < N.  lam_s carries the 1/(2 p_1) and both 1/M.
+template <class LineT>
+__device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const FFTTables<double>& tab,
+                                         const GSTables64& gs) {
+  constexpr int M = LineT::M, E = LineT::E, T = LineT::T;
+  const int t = L.t;
+  // v2 = Q^H ifft(lam_s o fft(Q v1))
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = cmul(d[m], gs.q[t + T * m]);
+  L.template transform<-1>(d, lds, tab);
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = cmul(d[m], gs.lam_s[t + T * m]);
+  L.template transform<+1>(d, lds, tab);
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = cmulc(d[m], gs.q[t + T * m]);
+  // v3 = ifft(lam_c o fft(v2))
+  L.template transform<-1>(d, lds, tab);
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = cmul(d[m], gs.lam_c[t + T * m]);
+  L.template transform<+1>(d, lds, tab);
+  // w = Re(v3) + J Im(v3); bordering correction w[:N] - f * w[N]
+  double* buf = reinterpret_cast<double*>(lds);
+#pragma unroll
+  for (int m = 0; m < E; ++m) L.put_real(buf, t + T * m, d[m].y);
+  if (t == T - 1) L.put_real(buf, M, d[E - 1].x);   // Re v3[M-1]
+  __syncthreads();
+  const double wN = L.get_real(buf, M) + L.get_real(buf, 0);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const double w = d[m].x + L.get_real(buf, M - 1 - k);
+    const double f = (k < M - 1) ? gs.f[k] : 0.0;
+    d[m].x = w - f * wN;
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------------
+// rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M
+template <int M>
+__global__ void __launch_bounds__(RowCfg<M>::NT)
+rows_fwd_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int n,
+                FFTTables<double> tab, const V* __restrict__ root2M) {
+  using L_t = typename RowCfg<M>::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
+  const L_t L(threadIdx.x);
+  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
+  const bool live = y < n;
+  const double* row = u + (size_t)(live ? y : 0) * ldu;
+  V d[E];
+  // z[m] = x[2m] + i x[2m+1]; x[n] = 0 for n >= N
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    const int m = L.t + T * c;
+    const int n0 = 2 * m, n1 = 2 * m + 1;
+    d[c].x = (live && n0 < n) ? row[n0] : 0.0;
+    d[c].y = (live && n1 < n) ? row[n1] : 0.0;
+  }
+  L.template transform<-1>(d, smem, tab);
+  // pair Z[k] with Z[M-k] through a half-length complex buffer in two rounds: slots
+  // m < E/2 hold k < M/2, the others k >= M/2; k = 0 and k = M/2 are their own partners.
+  V* zb = reinterpret_cast<V*>(smem);
+  V* out = S + (size_t)(live ? y : 0) * lds_;
+  auto emit = [&](int k, V zk, V zmk) {
+    const V zm = cconj(zmk);
+    const V ev = cscale(cadd(zk, zm), 0.5);
+    const V od = cscale(csub(zk, zm), 0.5);        // = i * FO[k]
+    const V fo = V{od.y, -od.x};                   // X[k] = FE[k] + W_P^k FO[k]
+    if (live) out[k] = cadd(ev, cmul(fo, root2M[k]));
+  };
+#pragma unroll
+  for (int round = 0; round < 2; ++round) {
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      const bool lower = c < E / 2;
+      if (lower == (round == 0)) {
+        const int k = L.t + T * c;
+        zb[L.cidx(lower ? k : k - M / 2)] = d[c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      const bool lower = c < E / 2;
+      const int k = L.t + T * c;
+      if (lower != (round == 0)) {
+        if (k == 0) {
+          emit(0, d[c], d[c]);
+          if (live) out[M] = V{d[c].x - d[c].y, 0.0};   // X[M] = Re Z0 - Im Z0
+        } else if (k == M / 2) {
+          emit(k, d[c], d[c]);
+        } else {
+          const int km = M - k;
+          emit(k, d[c], zb[L.cidx(lower ? km - M / 2 : km)]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// cols_conv: for every x-frequency column kx (0..M): c[y] = S[y][kx] (y < N, zero to P),
+// out = IFFT_P(Lambda[kx] o FFT_P(c)), first N rows.  The length-P transform is split
+// into its even and odd frequencies (two length-M transforms of c and W_P^y c), each
+// handled by its own line of the workgroup (lines 2g / 2g+1 for column group g).
+template <int M>
+__global__ void __launch_bounds__(ColConvCfg<M>::NT)
+cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
+                 FFTTables<double> tab, const V* __restrict__ root2M, int ngroups) {
+  using Cfg = ColConvCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  constexpr int CPW = Cfg::LPW / 2;  // columns per workgroup
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;
+  const L_t L(threadIdx.x);
+  const int col = grp * CPW + L.line / 2;
+  const int odd = L.line & 1;
+  const bool live = col <= M;   // M + 1 columns
+  const int colc = live ? col : M;
+  V d[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int y = L.t + T * m;
+    V c = (y < n) ? S[(size_t)y * lds_ + colc] : V{0.0, 0.0};
+    if (odd) c = cmul(c, root2M[y]);                 // W_P^y
+    d[m] = c;
+  }
+  L.template transform<-1>(d, smem, tab);
+  // eigenvalues of the embedding, row kx: [Lam_e(0..M/2), Lam_o(0..M/2-1)] (even, mirrored)
+  const double* lr = lam + (size_t)colc * ldlam;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = L.t + T * m;
+    const double s = odd ? lr[M / 2 + 1 + min(k, M - 1 - k)] : lr[min(k, M - k)];
+    d[m] = cscale(d[m], s);
+  }
+  L.template transform<+1>(d, smem, tab);
+  // combine: out[y] = even[y] + W_P^{-y} odd[y]; the two lines of a column share
+  // their exchange space as one complex buffer (complex index y * CPW + column slot)
+  V* xb = reinterpret_cast<V*>(smem);
+  static_assert(Cfg::LINE_FAST, "column pairing assumes interleaved lines");
+  const int slot = L.line / 2;
+  if (odd) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int y = L.t + T * m;
+      xb[y * CPW + slot] = cmulc(d[m], root2M[y]);
+    }
+  }
+  __syncthreads();
+  if (!odd && live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int y = L.t + T * m;
+      if (y < n) S[(size_t)y * lds_ + col] = cadd(d[m], xb[y * CPW + slot]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// rows_rhs_gs: x[n] = inverse rFFT_P of S row (Lambda carries 1/(P M)); B = sigma x +
+// gamma g(u) [+ tau phi2]; X = H^-1 B on the x-line.  MODE: 0 = step (n >= 1),
+// 1 = start-up step (n = 0, adds tau phi2), 2 = L_h only (X = sigma x, no solve).
+template <int M, int MODE>
+__global__ void __launch_bounds__(RowCfg<M>::NT)
+rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
+                   const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
+                   StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
+  using L_t = typename RowCfg<M>::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
+  const L_t L(threadIdx.x);
+  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
+  const bool live = y < n;
+  const int yy = live ? y : 0;
+  const V* srow = S + (size_t)yy * lds_;
+  V d[E];
+  // c2r pre-processing: Z[k] = FE[k] + i FO[k], FE = (X[k] + conj X[M-k])/2,
+  // FO = W_P^{-k} (X[k] - conj X[M-k])/2 ; the 1/2 is folded into Lambda
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = L.t + T * m;
+    const V xk = srow[k];
+    const V xm = cconj(srow[M - k]);
+    const V fe = cadd(xk, xm);
+    const V fo = cmulc(csub(xk, xm), root2M[k]);
+    d[m] = V{fe.x - fo.y, fe.y + fo.x};
+  }
+  L.template transform<+1>(d, smem, tab);
+  // slot m holds z[j], j = t + T m: x[2j] = Re, x[2j+1] = Im
+  const double* urow = u + (size_t)yy * ldu;
+  double* buf = reinterpret_cast<double*>(smem);
+  if constexpr (MODE == 2) {
+    if (live) {
+      double* xo = X + (size_t)y * ldx;
+#pragma unroll
+      for (int m = 0; m < E / 2; ++m) {
+        const int j = L.t + T * m;
+        if (2 * j < n) xo[2 * j] = sc.sigma * d[m].x;
+        if (2 * j + 1 < n) xo[2 * j + 1] = sc.sigma * d[m].y;
+      }
+    }
+    return;
+  } else {
+    const double* prow = (MODE == 1) ? phi2 + (size_t)yy * ldu : nullptr;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int j = L.t + T * m;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = 2 * j + h;
+        if (idx < M) {
+          double b = 0.0;
+          if (idx < n) {
+            const double xv = h ? d[m].y : d[m].x;
+            const double uv = urow[idx];
+            b = sc.sigma * xv + sc.gamma * g_of(uv, sc.gkind, sc.gparam);
+            if constexpr (MODE == 1) b += sc.tau * prow[idx];
+          }
+          L.put_real(buf, idx, b);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = L.t + T * m;
+      d[m] = V{L.get_real(buf, k), L.get_real(buf, M - 1 - k)};
+    }
+    __syncthreads();
+    gs_solve(L, d, smem, tab, gs);
+    if (live) {
+      double* xo = X + (size_t)y * ldx;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = L.t + T * m;
+        if (k < n) xo[k] = d[m].x;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// rows_gs: in-place H^-1 on nlines lines of length N (stride ld).
+template <int M>
+__global__ void __launch_bounds__(RowCfg<M>::NT)
+rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<double> tab, GSTables64 gs) {
+  using L_t = typename RowCfg<M>::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
+  const L_t L(threadIdx.x);
+  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
+  const bool live = y < nlines;
+  double* row = lines + (size_t)(live ? y : 0) * ld;
+  V d[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = L.t + T * m;
+    const int kr = M - 1 - k;
+    d[m].x = (live && k < n) ? row[k] : 0.0;
+    d[m].y = (live && kr < n) ? row[kr] : 0.0;
+  }
+  gs_solve(L, d, smem, tab, gs);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = L.t + T * m;
+      if (k < n) row[k] = d[m].x;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// cols_gs: y-line solves on the columns of X and the leapfrog update.
+// MODE 0: uout = 2 ucur - uprev + Uhat (uout may alias uprev); MODE 1: uout = ucur + Uhat.
+template <int M, int MODE>
+__global__ void __launch_bounds__(ColGSCfg<M>::NT)
+cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const double* uprev,
+               double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
+  using Cfg = ColGSCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;
+  const L_t L(threadIdx.x);
+  const int col = grp * Cfg::LPW + L.line;
+  const bool live = col < n;
+  const int cc = live ? col : 0;
+  V d[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = L.t + T * m;
+    const int kr = M - 1 - k;
+    d[m].x = (live && k < n) ? X[(size_t)k * ldx + cc] : 0.0;
+    d[m].y = (live && kr < n) ? X[(size_t)kr * ldx + cc] : 0.0;
+  }
+  gs_solve(L, d, smem, tab, gs);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = L.t + T * m;
+      if (k < n) {
+        const size_t o = (size_t)k * ldu + col;
+        const double uc = ucur[o];
+        if constexpr (MODE == 0) uout[o] = 2.0 * uc - uprev[o] + d[m].x;
+        else uout[o] = uc + d[m].x;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// host-side launchers
+template <int M>
+void launch_rows_fwd(const double* u, int ldu, V* S, int lds_, int n, const FFTTables<double>& tab,
+                     const V* root2M, hipStream_t st) {
+  const int grid = (n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
+  hipLaunchKernelGGL(rows_fwd_kernel<M>, dim3(grid), dim3(RowCfg<M>::NT), 0, st, u, ldu, S, lds_, n, tab, root2M);
+}
+
+template <int M>
+void launch_cols_conv(V* S, int lds_, int n, const double* lam, int ldlam, const FFTTables<double>& tab,
+                      const V* root2M, hipStream_t st) {
+  constexpr int CPW = ColConvCfg<M>::LPW / 2;
+  const int ngroups = (M + 1 + CPW - 1) / CPW;
+  const int grid = ((ngroups + 7) / 8) * 8;
+  hipLaunchKernelGGL(cols_conv_kernel<M>, dim3(grid), dim3(ColConvCfg<M>::NT), 0, st, S, lds_, n, lam, ldlam,
+                     tab, root2M, ngroups);
+}
+
+template <int M>
+void launch_rows_rhs_gs(int mode, const V* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
+                        int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const GSTables64& gs,
+                        const V* root2M, hipStream_t st) {
+  const int grid = (n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
+  if (mode == 0)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
+                       ldx, n, sc, tab, gs, root2M);
+  else if (mode == 1)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
+                       ldx, n, sc, tab, gs, root2M);
+  else
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 2>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
+                       ldx, n, sc, tab, gs, root2M);
+}
+
+template <int M>
+void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab, const GSTables64& gs,
+                    hipStream_t st) {
+  const int grid = (nlines + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
+  hipLaunchKernelGGL(rows_gs_kernel<M>, dim3(grid), dim3(RowCfg<M>::NT), 0, st, lines, ld, nlines, n, tab, gs);
+}
+
+template <int M>
+void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
+                    int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st) {
+  const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
+  const int grid = ((ngroups + 7) / 8) * 8;
+  if (mode == 0)
+    hipLaunchKernelGGL((cols_gs_kernel<M, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, uprev, uout,
+                       ldu, n, tab, gs, ngroups);
+  else
+    hipLaunchKernelGGL((cols_gs_kernel<M, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, uprev, uout,
+                       ldu, n, tab, gs, ngroups);
+}
+
+#define SADI_INSTANTIATE(M)                                                                                      \
+  template void launch_rows_fwd<M>(const double*, int, V*, int, int, const FFTTables<double>&, const V*,         \
+                                   hipStream_t);                                                                 \
+  template void launch_cols_conv<M>(V*, int, int, const double*, int, const FFTTables<double>&, const V*,        \
+                                    hipStream_t);                                                                \
+  template void launch_rows_rhs_gs<M>(int, const V*, int, const double*, int, const double*, double*, int, int,   \
+                                      const StepScalars&, const FFTTables<double>&, const GSTables64&, const V*,  \
+                                      hipStream_t);                                                              \
+  template void launch_rows_gs<M>(double*, int, int, int, const FFTTables<double>&, const GSTables64&,            \
+                                  hipStream_t);                                                                  \
+  template void launch_cols_gs<M>(int, const double*, int, const double*, const double*, double*, int, int,       \
+                                  const FFTTables<double>&, const GSTables64&, hipStream_t);
+
+SADI_FOR_EACH_M(SADI_INSTANTIATE)
+
+}  // namespace sadi

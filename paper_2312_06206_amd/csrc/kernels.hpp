@@ -1,0 +1,88 @@
+// Internal interface between the C ABI layer and the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+
+namespace sadi {
+
+// supported line lengths M = N + 1
+#define SADI_FOR_EACH_M(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+// tables of the Gohberg-Semencul line solve (FP64)
+struct GSTables64 {
+  const double2* q;      // Q = diag(e^{-i pi k / M}), k < M
+  const double2* lam_s;  // fft(Q s) / (2 p_1 M^2)... scaled, see the host setup
+  const double2* lam_c;  // fft(c) / M
+  const double* f;       // bordering correction (J c)[k] / p_1, k < N
+};
+
+// per-call scalars of the right-hand side B = sigma (L u) h^alpha + gamma g(u) [+ tau phi2]
+struct StepScalars {
+  double sigma;   // multiplies the BTTB convolution (carries -kappa tau^2 h^-alpha etc.)
+  double gamma;   // multiplies g(u)
+  double tau;     // start-up step: multiplies phi2
+  int gkind;      // 0: 0, 1: -sin u, 2: -u^3, 3: -gparam * u
+  double gparam;
+};
+
+__device__ __forceinline__ double g_of(double u, int kind, double p) {
+  switch (kind) {
+    case 1: return -sin(u);
+    case 2: return -u * u * u;
+    case 3: return -p * u;
+    default: return 0.0;
+  }
+}
+
+// launch shapes per kernel family
+template <int M> struct RowCfg {
+  static constexpr int T = M / Shape<M>::E;
+  static constexpr int LPW = T >= 256 ? 1 : 256 / T;
+  static constexpr bool LINE_FAST = false;
+  static constexpr int SPLIT = 2;
+  using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
+  static constexpr int NT = Line::NT;
+  static constexpr int LDS_BYTES = Line::LDS_BYTES;
+};
+
+// two lines (even / odd frequency halves) per column, >= 2 columns per workgroup
+template <int M> struct ColConvCfg {
+  static constexpr int T = M / Shape<M>::E;
+  static constexpr int LPW = (1024 / T) < 4 ? 4 : 1024 / T;
+  static constexpr bool LINE_FAST = true;
+  static constexpr int SPLIT = 2;
+  using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
+  static constexpr int NT = Line::NT;
+  static constexpr int LDS_BYTES = Line::LDS_BYTES;
+};
+
+// >= 4 columns per workgroup
+template <int M> struct ColGSCfg {
+  static constexpr int T = M / Shape<M>::E;
+  static constexpr int LPW = (1024 / T) < 4 ? 4 : 1024 / T;
+  static constexpr bool LINE_FAST = true;
+  static constexpr int SPLIT = 2;
+  using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
+  static constexpr int NT = Line::NT;
+  static constexpr int LDS_BYTES = Line::LDS_BYTES;
+};
+
+template <int M>
+void launch_rows_fwd(const double* u, int ldu, double2* S, int lds_, int n, const FFTTables<double>& tab,
+                     const double2* root2M, hipStream_t st);
+template <int M>
+void launch_cols_conv(double2* S, int lds_, int n, const double* lam, int ldlam, const FFTTables<double>& tab,
+                      const double2* root2M, hipStream_t st);
+template <int M>
+void launch_rows_rhs_gs(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
+                        int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const GSTables64& gs,
+                        const double2* root2M, hipStream_t st);
+template <int M>
+void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab, const GSTables64& gs,
+                    hipStream_t st);
+template <int M>
+void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
+                    int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
+
+}  // namespace sadi

@@ -1,0 +1,460 @@
+// C ABI of the S-ADI solver: context, setup, and the entry points of include/sadi.h.
+#include "../../include/sadi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "setup_math.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sadi_status fail(sadi_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define SADI_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(SADI_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool finite_all(std::initializer_list<double> v) {
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+bool supported_n(int n) {
+  const int m = n + 1;
+  return m >= 16 && m <= 4096 && (m & (m - 1)) == 0;
+}
+
+}  // namespace
+
+struct sadi_ctx {
+  int n = 0, m = 0;
+  double alpha = 0, kappa = 0, tau = 0, a = 0, b = 0, h = 0, h_alpha = 0, beta = 0;
+  sadi_g_kind g = SADI_G_NEG_SIN;
+  double g_param = 0.0;
+  sadi_precision prec = SADI_FP64;
+  hipStream_t stream = nullptr;
+  int magic = 0x5AD1;
+  long long device_bytes = 0;
+
+  // device data
+  double2* rootM = nullptr;    // T entries
+  double2* rootS = nullptr;    // E entries
+  double2* root2M = nullptr;   // M entries, e^{-2 pi i k / 2M}
+  double2* lam_s = nullptr;
+  double2* lam_c = nullptr;
+  double* f = nullptr;         // N
+  double* lam2d = nullptr;     // (M+1) rows x ldlam
+  int ldlam = 0;
+  double2* S = nullptr;        // N rows x ldS complex
+  int ldS = 0;
+  double* X = nullptr;         // N rows x ldX
+  int ldX = 0;
+
+  std::vector<void*> allocs;
+
+  sadi_status alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return fail(SADI_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    allocs.push_back(*p);
+    device_bytes += (long long)bytes;
+    return SADI_OK;
+  }
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+  }
+};
+
+namespace {
+
+bool ctx_ok(const sadi_ctx* c) { return c != nullptr && c->magic == 0x5AD1; }
+
+// ---------------------------------------------------------------------------------
+// dispatch on M
+template <template <int> class F, class... A>
+void dispatch_m(int m, A&&... args) {
+  switch (m) {
+#define SADI_CASE(MM) \
+  case MM:            \
+    F<MM>::run(std::forward<A>(args)...); \
+    break;
+    SADI_FOR_EACH_M(SADI_CASE)
+#undef SADI_CASE
+    default:
+      break;
+  }
+}
+
+template <int M> int threads_per_line() { return M / sadi::Shape<M>::E; }
+template <int M> int e_of() { return sadi::Shape<M>::E; }
+template <int M> int p2_of() { return sadi::Shape<M>::P2; }
+
+struct ShapeInfo {
+  int E, P2, T;
+};
+ShapeInfo shape_of(int m) {
+  switch (m) {
+#define SADI_SH(MM) \
+  case MM:          \
+    return ShapeInfo{sadi::Shape<MM>::E, sadi::Shape<MM>::P2, MM / sadi::Shape<MM>::E};
+    SADI_FOR_EACH_M(SADI_SH)
+#undef SADI_SH
+    default:
+      return ShapeInfo{0, 0, 0};
+  }
+}
+
+sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS}; }
+sadi::GSTables64 gs_tables(const sadi_ctx* c) {
+  return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f};
+}
+
+template <int M> struct RowsFwd {
+  static void run(const sadi_ctx* c, const double* u) {
+    sadi::launch_rows_fwd<M>(u, c->n, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
+  }
+};
+template <int M> struct ColsConv {
+  static void run(const sadi_ctx* c) {
+    sadi::launch_cols_conv<M>(c->S, c->ldS, c->n, c->lam2d, c->ldlam, tables(c), c->root2M, c->stream);
+  }
+};
+template <int M> struct RowsRhs {
+  static void run(const sadi_ctx* c, int mode, const double* u, const double* phi2, double* X, int ldx,
+                  const sadi::StepScalars& sc) {
+    sadi::launch_rows_rhs_gs<M>(mode, c->S, c->ldS, u, c->n, phi2, X, ldx, c->n, sc, tables(c), gs_tables(c),
+                                c->root2M, c->stream);
+  }
+};
+template <int M> struct ColsGS {
+  static void run(const sadi_ctx* c, int mode, const double* ucur, const double* uprev, double* uout) {
+    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, ucur, uprev, uout, c->n, c->n, tables(c), gs_tables(c), c->stream);
+  }
+};
+template <int M> struct RowsGS {
+  static void run(const sadi_ctx* c, double* lines, int ld, int nlines) {
+    sadi::launch_rows_gs<M>(lines, ld, nlines, c->n, tables(c), gs_tables(c), c->stream);
+  }
+};
+
+sadi_status check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return SADI_OK;
+}
+
+sadi::StepScalars scalars(const sadi_ctx* c, bool first) {
+  sadi::StepScalars sc{};
+  const double t2 = c->tau * c->tau;
+  const double w = first ? 0.5 : 1.0;
+  sc.sigma = -w * t2 * c->kappa * c->h_alpha;   // h_alpha = h^-alpha
+  sc.gamma = w * t2;
+  sc.tau = c->tau;
+  sc.gkind = (int)c->g;
+  sc.gparam = c->g_param;
+  return sc;
+}
+
+// one step of the delta form on the device; mode 0: uout = 2 ucur - uprev + Uhat,
+// mode 1 (start-up): uout = ucur + Uhat with phi2
+sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double* uprev, const double* phi2,
+                         double* uout) {
+  dispatch_m<RowsFwd>(c->m, c, ucur);
+  dispatch_m<ColsConv>(c->m, c);
+  const sadi::StepScalars sc = scalars(c, mode == 1);
+  dispatch_m<RowsRhs>(c->m, c, mode, ucur, phi2, c->X, c->ldX, sc);
+  dispatch_m<ColsGS>(c->m, c, mode, ucur, uprev, uout);
+  return check_launch();
+}
+
+sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2) {
+  if (!domain) return fail(SADI_E_INVALID, "domain is NULL");
+  if (!finite_all({alpha, kappa, tau, domain[0], domain[1]}))
+    return fail(SADI_E_INVALID, "non-finite parameter");
+  if (!(alpha > 1.0 && (alpha < 2.0 || (allow2 && alpha <= 2.0))))
+    return fail(SADI_E_INVALID, "alpha must lie in (1, 2)");
+  if (!(kappa > 0.0)) return fail(SADI_E_INVALID, "kappa must be positive");
+  if (!(tau > 0.0)) return fail(SADI_E_INVALID, "tau must be positive");
+  if (!(domain[1] > domain[0])) return fail(SADI_E_INVALID, "domain must satisfy b > a");
+  if (n < 1) return fail(SADI_E_INVALID, "N must be >= 1");
+  if (!supported_n(n)) return fail(SADI_E_UNSUPPORTED, "N + 1 must be a power of two in [16, 4096]");
+  return SADI_OK;
+}
+
+sadi_status build_ctx(double alpha, double kappa, int n, double tau, const double* domain,
+                      const std::vector<double>& a1, const std::vector<double>& a2, sadi_ctx** out) {
+  sadi_ctx* c = new (std::nothrow) sadi_ctx();
+  if (!c) return fail(SADI_E_NOMEM, "host allocation failed");
+  c->n = n;
+  c->m = n + 1;
+  c->alpha = alpha;
+  c->kappa = kappa;
+  c->tau = tau;
+  c->a = domain[0];
+  c->b = domain[1];
+  c->h = (c->b - c->a) / (n + 1);
+  c->h_alpha = std::pow(c->h, -alpha);
+  c->beta = kappa * tau * tau * c->h_alpha / 2.0;
+  const int m = c->m;
+  const ShapeInfo sh = shape_of(m);
+  auto bail = [&](sadi_status st) {
+    c->release();
+    delete c;
+    return st;
+  };
+
+  // ---- host tables
+  sadi::GSData gsd;
+  try {
+    gsd = sadi::gs_data(a1, n, c->beta);
+  } catch (const std::exception& e) {
+    return bail(fail(SADI_E_INVALID, std::string("line matrix: ") + e.what()));
+  }
+  const long double pi = 3.14159265358979323846264338327950288L;
+  std::vector<double2> hrootM(sh.T), hrootS(sh.E), hroot2M(m);
+  for (int j = 0; j < sh.T; ++j) {
+    const long double a = -2.0L * pi * j / m;
+    hrootM[j] = make_double2((double)std::cos(a), (double)std::sin(a));
+  }
+  for (int j = 0; j < sh.E; ++j) {
+    const long double a = -2.0L * pi * j / (sh.E * sh.P2);
+    hrootS[j] = make_double2((double)std::cos(a), (double)std::sin(a));
+  }
+  for (int k = 0; k < m; ++k) {
+    const long double a = -pi * k / m;
+    hroot2M[k] = make_double2((double)std::cos(a), (double)std::sin(a));
+  }
+  std::vector<double2> hls(m), hlc(m);
+  for (int k = 0; k < m; ++k) {
+    hls[k] = make_double2(gsd.lam_s[k].real(), gsd.lam_s[k].imag());
+    hlc[k] = make_double2(gsd.lam_c[k].real(), gsd.lam_c[k].imag());
+  }
+  c->ldlam = m + 1 + ((8 - (m + 1) % 8) % 8);
+  std::vector<double> hlam((size_t)(m + 1) * c->ldlam, 0.0);
+  sadi::bccb_eigenvalues(a2, n, hlam.data(), c->ldlam);
+
+  // ---- device allocations
+  c->ldS = m + 8;           // complex elements per row of the half spectrum (>= M+1)
+  c->ldX = m;
+  sadi_status st;
+  if ((st = c->alloc((void**)&c->rootM, sizeof(double2) * sh.T)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->rootS, sizeof(double2) * sh.E)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->root2M, sizeof(double2) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->lam_s, sizeof(double2) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->lam_c, sizeof(double2) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->f, sizeof(double) * n)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)n * c->ldS)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)n * c->ldX)) != SADI_OK) return bail(st);
+
+  auto up = [&](void* dst, const void* src, size_t bytes) -> sadi_status {
+    hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    return SADI_OK;
+  };
+  if ((st = up(c->rootM, hrootM.data(), sizeof(double2) * sh.T)) != SADI_OK) return bail(st);
+  if ((st = up(c->rootS, hrootS.data(), sizeof(double2) * sh.E)) != SADI_OK) return bail(st);
+  if ((st = up(c->root2M, hroot2M.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->lam_s, hls.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->lam_c, hlc.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->f, gsd.f.data(), sizeof(double) * n)) != SADI_OK) return bail(st);
+  if ((st = up(c->lam2d, hlam.data(), sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
+  *out = c;
+  return SADI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sadi_last_error(void) { return g_last_error.c_str(); }
+
+sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const double* domain, sadi_ctx** out) {
+  if (!out) return fail(SADI_E_INVALID, "out is NULL");
+  *out = nullptr;
+  sadi_status st = validate_problem(alpha, kappa, n, tau, domain, false);
+  if (st != SADI_OK) return st;
+  try {
+    const std::vector<double> a1 = sadi::riesz_coeffs(alpha, n + 1);
+    const std::vector<double> a2 = sadi::laplacian_coeffs(alpha, n);
+    return build_ctx(alpha, kappa, n, tau, domain, a1, a2, out);
+  } catch (const std::bad_alloc&) {
+    return fail(SADI_E_NOMEM, "host allocation failed in setup");
+  } catch (const std::exception& e) {
+    return fail(SADI_E_INVALID, std::string("setup: ") + e.what());
+  }
+}
+
+sadi_status sadi_setup_with_coeffs(double alpha, double kappa, int n, double tau, const double* domain,
+                                   const double* a1, const double* a2, sadi_ctx** out) {
+  if (!out) return fail(SADI_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!a1 || !a2) return fail(SADI_E_INVALID, "coefficient table is NULL");
+  sadi_status st = validate_problem(alpha, kappa, n, tau, domain, true);
+  if (st != SADI_OK) return st;
+  try {
+    std::vector<double> v1(a1, a1 + n + 1), v2(a2, a2 + (size_t)n * n);
+    return build_ctx(alpha, kappa, n, tau, domain, v1, v2, out);
+  } catch (const std::bad_alloc&) {
+    return fail(SADI_E_NOMEM, "host allocation failed in setup");
+  } catch (const std::exception& e) {
+    return fail(SADI_E_INVALID, std::string("setup: ") + e.what());
+  }
+}
+
+sadi_status sadi_set_options(sadi_ctx* c, sadi_g_kind g, double g_param, sadi_precision prec) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if ((int)g < 0 || (int)g > 3) return fail(SADI_E_INVALID, "unknown g kind");
+  if ((int)prec < 0 || (int)prec > 2) return fail(SADI_E_INVALID, "unknown precision");
+  if (!std::isfinite(g_param)) return fail(SADI_E_INVALID, "g_param must be finite");
+  if (prec != SADI_FP64) return fail(SADI_E_UNSUPPORTED, "only float64 line solves are built");
+  c->g = g;
+  c->g_param = g_param;
+  c->prec = prec;
+  return SADI_OK;
+}
+
+sadi_status sadi_set_stream(sadi_ctx* c, void* s) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  c->stream = (hipStream_t)s;
+  return SADI_OK;
+}
+
+sadi_status sadi_first_step(sadi_ctx* c, const double* phi1, const double* phi2, double* u1) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (!phi1 || !phi2 || !u1) return fail(SADI_E_INVALID, "NULL array");
+  if (u1 == phi1 || u1 == phi2) return fail(SADI_E_INVALID, "u1 must not alias phi1 or phi2");
+  return enqueue_step(c, 1, phi1, nullptr, phi2, u1);
+}
+
+sadi_status sadi_step(sadi_ctx* c, double* u_prev, const double* u_cur) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (!u_prev || !u_cur) return fail(SADI_E_INVALID, "NULL array");
+  if (u_prev == u_cur) return fail(SADI_E_INVALID, "u_prev and u_cur must differ");
+  return enqueue_step(c, 0, u_cur, u_prev, nullptr, u_prev);
+}
+
+sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (!u_prev || !u_cur) return fail(SADI_E_INVALID, "NULL array");
+  if (u_prev == u_cur) return fail(SADI_E_INVALID, "u_prev and u_cur must differ");
+  if (nsteps < 0) return fail(SADI_E_INVALID, "nsteps must be >= 0");
+  double* a = u_prev;
+  double* b = u_cur;
+  for (int s = 0; s < nsteps; ++s) {
+    sadi_status st = enqueue_step(c, 0, b, a, nullptr, a);
+    if (st != SADI_OK) return st;
+    std::swap(a, b);
+  }
+  if (nsteps % 2 == 1) {
+    // newest is in u_prev's buffer: exchange the two arrays through the X workspace
+    const size_t w = sizeof(double) * c->n, hgt = c->n;
+    SADI_HIP(hipMemcpy2DAsync(c->X, sizeof(double) * c->ldX, u_cur, w, w, hgt, hipMemcpyDeviceToDevice, c->stream));
+    SADI_HIP(hipMemcpyAsync(u_cur, u_prev, w * hgt, hipMemcpyDeviceToDevice, c->stream));
+    SADI_HIP(hipMemcpy2DAsync(u_prev, w, c->X, sizeof(double) * c->ldX, w, hgt, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return SADI_OK;
+}
+
+sadi_status sadi_toeplitz_solve(sadi_ctx* c, double* lines, int nlines, int ld) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (nlines < 0) return fail(SADI_E_INVALID, "nlines must be >= 0");
+  if (nlines == 0) return SADI_OK;
+  if (!lines) return fail(SADI_E_INVALID, "NULL array");
+  if (ld < c->n) return fail(SADI_E_INVALID, "ld must be >= N");
+  dispatch_m<RowsGS>(c->m, c, lines, ld, nlines);
+  return check_launch();
+}
+
+sadi_status sadi_apply_lh(sadi_ctx* c, const double* u, double* out) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (!u || !out) return fail(SADI_E_INVALID, "NULL array");
+  if (u == out) return fail(SADI_E_INVALID, "u and out must differ");
+  dispatch_m<RowsFwd>(c->m, c, u);
+  dispatch_m<ColsConv>(c->m, c);
+  sadi::StepScalars sc{};
+  sc.sigma = c->h_alpha;
+  dispatch_m<RowsRhs>(c->m, c, 2, u, (const double*)nullptr, out, c->n, sc);
+  return check_launch();
+}
+
+sadi_status sadi_get_info(const sadi_ctx* c, int* n, int* m, long long* bytes) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (n) *n = c->n;
+  if (m) *m = c->m;
+  if (bytes) *bytes = c->device_bytes;
+  return SADI_OK;
+}
+
+sadi_status sadi_destroy(sadi_ctx* c) {
+  if (!c) return SADI_OK;
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  c->magic = 0;
+  c->release();
+  delete c;
+  if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return SADI_OK;
+}
+
+// ---- host-only helpers ------------------------------------------------------------
+sadi_status sadi_host_riesz_coeffs(double alpha, int count, double* out) {
+  if (!out || count < 0) return fail(SADI_E_INVALID, "bad arguments");
+  if (!(alpha > 0.0 && alpha <= 2.0) || !std::isfinite(alpha)) return fail(SADI_E_INVALID, "alpha out of range");
+  const std::vector<double> a = sadi::riesz_coeffs(alpha, count);
+  std::memcpy(out, a.data(), sizeof(double) * a.size());
+  return SADI_OK;
+}
+
+sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out) {
+  if (!out || n < 1) return fail(SADI_E_INVALID, "bad arguments");
+  if (!(alpha > 1.0 && alpha < 2.0)) return fail(SADI_E_INVALID, "alpha must lie in (1, 2)");
+  if (n > 8192) return fail(SADI_E_UNSUPPORTED, "n too large");
+  try {
+    const std::vector<double> a = sadi::laplacian_coeffs(alpha, n);
+    std::memcpy(out, a.data(), sizeof(double) * a.size());
+  } catch (const std::bad_alloc&) {
+    return fail(SADI_E_NOMEM, "host allocation failed");
+  }
+  return SADI_OK;
+}
+
+sadi_status sadi_host_line_generator(double alpha, double kappa, int n, double tau, const double* domain,
+                                     double* out) {
+  if (!out) return fail(SADI_E_INVALID, "out is NULL");
+  sadi_status st = validate_problem(alpha, kappa, n, tau, domain, false);
+  if (st != SADI_OK && st != SADI_E_UNSUPPORTED) return st;
+  try {
+    const double h = (domain[1] - domain[0]) / (n + 1);
+    const double beta = kappa * tau * tau * std::pow(h, -alpha) / 2.0;
+    const std::vector<double> a1 = sadi::riesz_coeffs(alpha, n + 1);
+    std::vector<long double> t(n + 1);
+    for (int k = 0; k <= n; ++k) t[k] = (k == 0 ? 1.0L : 0.0L) + (long double)beta * a1[k];
+    const std::vector<long double> cc = sadi::toeplitz_first_column_inverse(t);
+    for (int k = 0; k <= n; ++k) out[k] = (double)cc[k];
+  } catch (const std::exception& e) {
+    return fail(SADI_E_INVALID, std::string("line generator: ") + e.what());
+  }
+  return SADI_OK;
+}
+
+}  // extern "C"

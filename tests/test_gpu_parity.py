@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.  Needs a GPU."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coeffs as C
+from oracle import scheme as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(G):
+    """oracle array G[i, j] -> device layout [j, i] (x fastest)."""
+    return torch.from_numpy(np.ascontiguousarray(G.T)).to(_dev())
+
+
+def from_dev(t):
+    return t.detach().cpu().numpy().T.copy()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+_problems = {}
+
+
+def oracle_problem(alpha, n, tau, kappa=1.0, g="neg_sin", domain=(-1.0, 1.0), g_param=0.0):
+    key = (alpha, n, tau, kappa, g, domain, g_param)
+    if key not in _problems:
+        _problems[key] = S.Problem(alpha=alpha, kappa=kappa, n=n, tau=tau, g=g, domain=domain, g_param=g_param)
+    return _problems[key]
+
+
+def solver(alpha, n, tau, kappa=1.0, g="neg_sin", domain=(-1.0, 1.0), g_param=0.0, **kw):
+    from paper_2312_06206_amd import Solver
+    _dev()
+    return Solver(alpha, kappa, n, tau, domain, g=g, g_param=g_param, **kw)
+
+
+# ------------------------------------------------------------------ line solves
+@pytest.mark.parametrize("n,alpha", [(15, 1.5), (63, 1.2), (255, 1.8), (1023, 1.5), (4095, 1.5), (4095, 1.8)])
+def test_toeplitz_solve(n, alpha):
+    _say(f"toeplitz_solve n={n} alpha={alpha}")
+    tau = 1e-3 if n > 63 else 1 / 64
+    P = oracle_problem(alpha, n, tau)
+    nl = 37
+    V = W.random_lines(nl, n, seed=n)
+    ref = P.line_solve(V)
+    with solver(alpha, n, tau) as s:
+        # ragged leading dimension
+        buf = torch.zeros((nl, n + 5), dtype=torch.float64, device=_dev())
+        buf[:, :n] = torch.from_numpy(V).to(_dev())
+        s.toeplitz_solve(buf)
+        got = buf[:, :n].cpu().numpy()
+        assert torch.all(buf[:, n:] == 0)
+    assert rel(got, ref) < 1e-13
+
+
+# ------------------------------------------------------------------ BTTB product
+@pytest.mark.parametrize("n,alpha", [(15, 1.5), (31, 1.1), (63, 1.9), (255, 1.5), (1023, 1.3)])
+def test_apply_lh(n, alpha):
+    _say(f"apply_lh n={n} alpha={alpha}")
+    P = oracle_problem(alpha, n, 1e-3)
+    U = W.asymmetric_field(n, seed=11)
+    ref = P.lh_apply(U)
+    with solver(alpha, n, 1e-3) as s:
+        got = from_dev(s.apply_lh(to_dev(U)))
+    assert rel(got, ref) < 1e-13
+
+
+# ------------------------------------------------------------------ single steps
+@pytest.mark.parametrize("n,alpha,tau,g", [(15, 1.5, 1 / 16, "neg_sin"), (63, 1.5, 1 / 64, "neg_sin"),
+                                          (255, 1.7, 1e-3, "neg_cube"), (1023, 1.2, 1e-3, "neg_sin")])
+def test_first_step_and_step(n, alpha, tau, g):
+    _say(f"steps n={n} alpha={alpha} g={g}")
+    P = oracle_problem(alpha, n, tau, kappa=1.3, g=g)
+    U0 = W.asymmetric_field(n, seed=1)
+    Phi2 = 0.7 * W.asymmetric_field(n, seed=2)
+    U1 = P.first_step(U0, Phi2)
+    U2 = P.step(U0, U1)
+    with solver(alpha, n, tau, kappa=1.3, g=g) as s:
+        d1 = s.first_step(to_dev(U0), to_dev(Phi2))
+        g1 = from_dev(d1)
+        # step from the oracle's own (u^0, u^1): identical inputs
+        up = to_dev(U0)
+        s.step(up, to_dev(U1))
+        g2 = from_dev(up)
+    assert rel(g1, U1) < 1e-12
+    assert rel(g1 - U0, U1 - U0) < 1e-12          # the increment Uhat alone
+    assert rel(g2, U2) < 1e-12
+    assert rel(g2 - 2 * U1 + U0, U2 - 2 * U1 + U0) < 1e-11
+
+
+# ------------------------------------------------------------------ whole runs
+def test_config1_run():
+    """Omega=(-1,1)^2, N=63, alpha=1.5, kappa=1, g=-sin u, phi1=exp(-10 r^2), phi2=0, tau=1/64, 64 steps."""
+    wl = W.CONFIG1
+    _say("config1 run")
+    P = oracle_problem(wl.alpha, wl.n, wl.tau)
+    phi1, phi2 = wl.phi1(), wl.phi2()
+    ref_prev, ref_cur = P.run(phi1, phi2, wl.steps)
+    with solver(wl.alpha, wl.n, wl.tau) as s:
+        u0 = to_dev(phi1)
+        u1 = s.first_step(u0, to_dev(phi2))
+        s.run(u0, u1, wl.steps - 1)
+        got_prev, got_cur = from_dev(u0), from_dev(u1)
+    assert rel(got_cur, ref_cur) < 1e-10
+    assert rel(got_prev, ref_prev) < 1e-10
+
+
+@pytest.mark.parametrize("nsteps", [6, 7])
+def test_run_even_and_odd_counts(nsteps):
+    n, alpha, tau = 127, 1.6, 2e-3
+    _say(f"run parity n={n} steps={nsteps}")
+    P = oracle_problem(alpha, n, tau)
+    U0 = W.asymmetric_field(n, seed=5)
+    Phi2 = 0.2 * W.asymmetric_field(n, seed=6)
+    ref_prev, ref_cur = P.run(U0, Phi2, nsteps + 1)
+    with solver(alpha, n, tau) as s:
+        u0 = to_dev(U0)
+        u1 = s.first_step(u0, to_dev(Phi2))
+        s.run(u0, u1, nsteps)
+        assert rel(from_dev(u1), ref_cur) < 1e-11
+        assert rel(from_dev(u0), ref_prev) < 1e-11
+
+
+def test_energy_conserved_on_gpu():
+    """g = 0: the discrete energy of the stability proof stays constant along the GPU run."""
+    n, alpha, tau = 127, 1.5, 5e-3
+    _say("energy")
+    P = oracle_problem(alpha, n, tau, g="zero")
+    U0 = W.asymmetric_field(n, seed=9)
+    Phi2 = 0.5 * W.asymmetric_field(n, seed=10)
+    with solver(alpha, n, tau, g="zero") as s:
+        u0 = to_dev(U0)
+        u1 = s.first_step(u0, to_dev(Phi2))
+        E0 = P.energy(from_dev(u0), from_dev(u1))
+        s.run(u0, u1, 200)
+        E1 = P.energy(from_dev(u0), from_dev(u1))
+    assert abs(E1 - E0) <= 1e-12 * E0
+
+
+def test_deterministic():
+    n, alpha, tau = 255, 1.5, 1e-3
+    _say("determinism")
+    U0 = W.asymmetric_field(n, seed=3)
+    outs = []
+    with solver(alpha, n, tau) as s:
+        for _ in range(2):
+            u0 = to_dev(U0)
+            u1 = s.first_step(u0, torch.zeros_like(u0))
+            s.run(u0, u1, 10)
+            outs.append(u1.cpu())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_alpha2_injected_coefficients_dst_closed_form():
+    """alpha = 2 tables injected through sadi_setup_with_coeffs; every operator is diagonal in
+    the DST-I basis and each mode follows a two-term recurrence solved in closed form."""
+    import scipy.fft
+    n, tau, kappa, m, steps = 63, 0.02, 0.8, 0.7, 30
+    _say("alpha=2 DST")
+    a1 = np.zeros(n + 1)
+    a1[:2] = [2.0, -1.0]
+    a2 = np.zeros((n, n))
+    a2[0, 0], a2[1, 0], a2[0, 1] = 4.0, -1.0, -1.0
+    U0 = W.asymmetric_field(n, seed=7)
+    Phi2 = W.asymmetric_field(n, seed=8)
+    with solver(2.0, n, tau, kappa=kappa, g="neg_linear", g_param=m, a1=a1, a2=a2) as s:
+        u0 = to_dev(U0)
+        u1 = s.first_step(u0, to_dev(Phi2))
+        s.run(u0, u1, steps - 1)
+        got = from_dev(u1)
+    h = 2.0 / (n + 1)
+    k = np.arange(1, n + 1)
+    mu = 4.0 * np.sin(k * np.pi / (2 * (n + 1))) ** 2
+    beta = kappa * tau * tau / (2 * h * h)
+    lam = (mu[:, None] + mu[None, :]) / (h * h)
+    den = (1 + beta * mu[:, None]) * (1 + beta * mu[None, :])
+    dst = lambda X: scipy.fft.dstn(X, type=1, norm="ortho")
+    c0, p2 = dst(U0), dst(Phi2)
+    c1 = c0 + (tau * p2 - 0.5 * tau * tau * (kappa * lam + m) * c0) / den
+    rho = tau * tau * (kappa * lam + m) / den
+    theta = np.arccos(1.0 - rho / 2.0)
+    B = (c1 - c0 * np.cos(theta)) / np.sin(theta)
+    ref = dst(c0 * np.cos(steps * theta) + B * np.sin(steps * theta))
+    assert rel(got, ref) < 1e-11
+
+
+# ------------------------------------------------------------------ full size
+@pytest.mark.parametrize("alpha", [1.5])
+def test_full_size_step_parity(alpha):
+    """N = 4095 (the benchmark's grid): the start-up step and one step n >= 1 against the
+    oracle's FFT tier, from identical inputs."""
+    wl = W.config2(4095, alpha, seed=0)
+    _say(f"full size step parity alpha={alpha}")
+    P = oracle_problem(wl.alpha, wl.n, wl.tau)
+    phi1 = W.asymmetric_field(wl.n, seed=21) + wl.phi1()
+    phi2 = 0.1 * W.asymmetric_field(wl.n, seed=22)
+    U1 = P.first_step(phi1, phi2)
+    with solver(wl.alpha, wl.n, wl.tau) as s:
+        u0 = to_dev(phi1)
+        u1 = s.first_step(u0, to_dev(phi2))
+        g1 = from_dev(u1)
+        assert rel(g1, U1) < 1e-12
+        assert rel(g1 - phi1, U1 - phi1) < 1e-11
+        U2 = P.step(phi1, U1)
+        s.step(u0, to_dev(U1))
+        g2 = from_dev(u0)
+    assert rel(g2, U2) < 1e-12
+    assert rel(g2 - 2 * U1 + phi1, U2 - 2 * U1 + phi1) < 1e-10

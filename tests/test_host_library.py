@@ -1,0 +1,99 @@
+"""CPU-only checks of libsadi.so: it loads, exports every symbol of include/sadi.h, its host
+setup mathematics agrees with the oracle, and argument validation fails cleanly."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import paper_2312_06206_amd as P
+from paper_2312_06206_amd import binding
+from oracle import coeffs as C
+
+
+def _declared_symbols():
+    src = open(binding.HEADER_PATH).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sadi_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("alpha", [1.1, 1.5, 1.9])
+def test_host_riesz_coeffs_match_oracle(alpha):
+    a = P.host_riesz_coeffs(alpha, 4096)
+    r = C.riesz_coeffs(alpha, 4096)
+    assert (np.abs(a - r) / np.abs(r)).max() < 1e-15
+
+
+@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8])
+def test_host_laplacian_coeffs_match_oracle(alpha):
+    n = 700
+    a = P.host_laplacian_coeffs(alpha, n)
+    r = C.laplacian_coeffs(alpha, n)
+    rel = np.abs(a - r) / np.abs(r)
+    assert rel[:40, :40].max() < 1e-14
+    assert rel.max() < 1e-13
+
+
+def test_host_laplacian_coeffs_full_size():
+    a = P.host_laplacian_coeffs(1.5, 4095)
+    r = C.laplacian_coeffs(1.5, 4095)
+    rel = np.abs(a - r) / np.abs(r)
+    assert rel[:64, :64].max() < 1e-14
+    assert rel.max() < 5e-13      # the oracle's Bessel values lose ~1e-13 at orders ~4e3
+    assert np.array_equal(a, a.T)
+
+
+@pytest.mark.parametrize("alpha,n", [(1.2, 63), (1.8, 1023)])
+def test_host_line_generator_is_first_column_of_inverse(alpha, n):
+    tau, kappa = 1e-3, 1.1
+    g = P.host_line_generator(alpha, kappa, n, tau)
+    h = 2.0 / (n + 1)
+    H = np.eye(n + 1) + 0.5 * kappa * tau * tau * h ** (-alpha) * scipy.linalg.toeplitz(C.riesz_coeffs(alpha, n + 1))
+    c = scipy.linalg.solve(H, np.eye(n + 1)[:, 0], assume_a="pos")
+    assert np.abs(g - c).max() <= 1e-15 * np.abs(c).max()
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0.9, 1.0, 63, 1e-3, (-1.0, 1.0)), -1),      # alpha out of (1,2)
+    ((2.0, 1.0, 63, 1e-3, (-1.0, 1.0)), -1),      # alpha = 2 only with injected tables
+    ((1.5, -1.0, 63, 1e-3, (-1.0, 1.0)), -1),     # kappa <= 0
+    ((1.5, 1.0, 63, 0.0, (-1.0, 1.0)), -1),       # tau <= 0
+    ((1.5, 1.0, 63, 1e-3, (1.0, -1.0)), -1),      # b <= a
+    ((1.5, 1.0, 63, float("nan"), (-1.0, 1.0)), -1),
+    ((1.5, 1.0, 0, 1e-3, (-1.0, 1.0)), -1),       # N < 1
+    ((1.5, 1.0, 100, 1e-3, (-1.0, 1.0)), -4),     # N + 1 not a power of two
+    ((1.5, 1.0, 8191, 1e-3, (-1.0, 1.0)), -4),    # too large
+])
+def test_setup_rejects_bad_arguments_without_touching_the_gpu(args, status):
+    lib = P.load_library()
+    alpha, kappa, n, tau, dom = args
+    d = np.asarray(dom, dtype=np.float64)
+    ctx = ctypes.c_void_p(123)
+    st = lib.sadi_setup(alpha, kappa, n, tau, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(ctx))
+    assert st == status
+    assert ctx.value is None
+    assert lib.sadi_last_error().decode() != ""
+
+
+def test_calls_on_null_context_fail_with_state_error():
+    lib = P.load_library()
+    assert lib.sadi_step(None, None, None) == -5
+    assert lib.sadi_run(None, None, None, 1) == -5
+    assert lib.sadi_toeplitz_solve(None, None, 1, 1) == -5
+    assert lib.sadi_destroy(None) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(ImportError):
+        binding.load_library()
