@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: S-ADI grid-point-steps/s on one MI355X.
+
+Workload (one GPU): Omega = (-1,1)^2, N = 4095 interior nodes per direction, alpha = 1.5,
+kappa = 1, g(u) = -sin u, phi1 a centred Gaussian bump whose width is drawn U[0.05, 0.3]
+from the seed, phi2 = 0, tau = 1e-3.  A "step" is one whole S-ADI step (BTTB product,
+right-hand side, x-line and y-line Gohberg-Semencul solves, leapfrog update).  The
+state is resident in HBM before the timed region; setup is timed separately.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  `roofline` covers the kernel with the largest share of the
+step, timed with HIP events on the library's stream inside the timed region;
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+METRIC = "S-ADI grid-point-steps/s at N=4095 (FP64 vs FP32+refine), % HBM roofline"
+
+
+def algorithmic_bytes(n: int) -> dict:
+    """Compulsory HBM bytes per launch of each kernel (float64 state, complex128 half
+    spectrum of N rows x (M+1) columns, (M+1)^2 BCCB eigenvalues)."""
+    m = n + 1
+    pts = n * n
+    spec = n * (m + 1) * 16
+    return {
+        "rows_fwd": pts * 8 + spec,                          # read u, write spectrum
+        "cols_conv": 2 * spec + (m + 1) * (m + 1) * 8,      # read+write spectrum, eigenvalues
+        "rows_rhs_gs": spec + pts * 8 + pts * 8,            # read spectrum, u; write X
+        "cols_gs": 4 * pts * 8,                             # read X, u^n, u^{n-1}; write u^{n+1}
+    }
+
+
+def traffic_record(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel sources (else None)."""
+    try:
+        from paper_2312_06206_amd import profiling
+        return profiling.traffic_for(kernel)
+    except Exception:
+        return None
+
+
+def cpu_baseline(wl, sample_steps: int) -> dict:
+    import numpy as np
+    import scipy.fft
+    from threadpoolctl import threadpool_limits, threadpool_info
+
+    from oracle import scheme as S
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    with threadpool_limits(limits=threads), scipy.fft.set_workers(threads):
+        P = S.Problem(alpha=wl.alpha, kappa=wl.kappa, n=wl.n, tau=wl.tau, g=wl.g, domain=wl.domain)
+        u0 = wl.phi1()
+        u1 = P.first_step(u0, wl.phi2())       # untimed: also builds the explicit H^-1
+        prev, cur = u0, u1
+        t0 = time.perf_counter()
+        for _ in range(sample_steps):
+            prev, cur = cur, P.step_delta(prev, cur, gemm=True)
+        dt = time.perf_counter() - t0
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    pts = wl.n * wl.n * sample_steps
+    return {"value": pts / dt, "unit": "grid-point-steps/s", "cores": int(max(blas, threads)), "kind": "oracle",
+            "sample": f"{sample_steps} steps n>=1 of the same N={wl.n} workload after the start-up step "
+                      f"(setup and explicit H^-1 excluded), {dt:.1f} s wall, numpy/scipy FP64 with "
+                      f"{threads} FFT workers and BLAS threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=4095)
+    ap.add_argument("--alpha", type=float, default=1.5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the slab decomposition is described in DESIGN.md but not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2312_06206_amd import Solver
+
+    dev = torch.device("cuda:0")
+    wl = W.config2(args.n, args.alpha, seed=args.seed, steps=args.steps)
+
+    t0 = time.perf_counter()
+    s = Solver(wl.alpha, wl.kappa, wl.n, wl.tau, wl.domain, g=wl.g)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    u0 = torch.from_numpy(np.ascontiguousarray(wl.phi1().T)).to(dev)
+    phi2 = torch.zeros_like(u0)
+    u1 = s.first_step(u0, phi2)
+    steps = args.steps + (args.steps % 2)    # even: no array exchange at the end of a run
+    if args.warmup:
+        s.run(u0, u1, args.warmup + (args.warmup % 2))
+    torch.cuda.synchronize()
+
+    s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(u0, u1, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ktimes = s.kernel_times()
+    s.set_kernel_timing(False)
+    finite = bool(torch.isfinite(u1).all().item())
+
+    n = wl.n
+    value = n * n * steps / dt
+    ms_per_step = 1e3 * dt / steps
+    alg = algorithmic_bytes(n)
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    avg_ms = ktimes[dom][0] / max(ktimes[dom][1], 1)
+    achieved = alg[dom] / (avg_ms * 1e-3) / 1e9
+    total_alg = sum(alg.values())
+    step_gbs = total_alg / (ms_per_step * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"S-ADI FP64 single instance, Omega=(-1,1)^2, N={n}, alpha={wl.alpha}, kappa=1, "
+                               f"g=-sin u, seeded Gaussian phi1 (width {W.seeded_width(args.seed):.4f}), phi2=0, "
+                               f"tau=1e-3",
+                   "N": n, "alpha": wl.alpha, "tau": wl.tau, "precision": "fp64", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record(dom)},
+        "step_roofline": {"algorithmic_bytes_per_step": total_alg, "achieved_GBps": step_gbs,
+                          "frac": step_gbs / HBM_PEAK_GBS},
+        "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
+        "setup_s": setup_s,
+        "finite": finite,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -111,6 +111,18 @@ sadi_status sadi_toeplitz_solve(sadi_ctx* ctx, double* lines, int nlines, int ld
  * no aliasing. */
 sadi_status sadi_apply_lh(sadi_ctx* ctx, const double* u, double* out);
 
+/* Per-kernel timing (observability).  When enabled, sadi_first_step / sadi_step /
+ * sadi_run record HIP events on the context's stream between the kernels of every
+ * step (one event before the first kernel and one after each kernel), so each
+ * kernel's device time is the difference of consecutive events.  Enabling resets
+ * the accumulators; events are created on demand (at most 8192 steps are kept).
+ * sadi_get_kernel_times synchronises the stream and writes, for the four kernels
+ * of a step -- 0 row forward transforms, 1 column convolution, 2 row inverse
+ * transforms + right-hand side + x-line solves, 3 y-line solves + update --
+ * the summed milliseconds (ms[4]) and the number of launches timed (count[4]). */
+sadi_status sadi_set_kernel_timing(sadi_ctx* ctx, int enable);
+sadi_status sadi_get_kernel_times(sadi_ctx* ctx, double* ms, long long* count);
+
 /* Sizes of the context: N, M = N+1, and device bytes held (any pointer may be NULL). */
 sadi_status sadi_get_info(const sadi_ctx* ctx, int* n, int* m, long long* device_bytes);
 

@@ -53,6 +53,8 @@ def load_library() -> ctypes.CDLL:
         "sadi_toeplitz_solve": (I, [VP, VP, I, I]),
         "sadi_apply_lh": (I, [VP, VP, VP]),
         "sadi_get_info": (I, [VP, P(I), P(I), P(ctypes.c_longlong)]),
+        "sadi_set_kernel_timing": (I, [VP, I]),
+        "sadi_get_kernel_times": (I, [VP, DP, P(ctypes.c_longlong)]),
         "sadi_destroy": (I, [VP]),
         "sadi_last_error": (ctypes.c_char_p, []),
         "sadi_host_riesz_coeffs": (I, [D, I, DP]),
@@ -145,6 +147,18 @@ class Solver:
         n, m, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
         _check(load_library().sadi_get_info(self._ctx, ctypes.byref(n), ctypes.byref(m), ctypes.byref(b)))
         return {"n": n.value, "m": m.value, "device_bytes": b.value}
+
+    KERNELS = ("rows_fwd", "cols_conv", "rows_rhs_gs", "cols_gs")
+
+    def set_kernel_timing(self, enable: bool = True):
+        _check(load_library().sadi_set_kernel_timing(self._ctx, int(bool(enable))))
+
+    def kernel_times(self):
+        """{kernel: (total_ms, launches)} of the steps enqueued since timing was enabled."""
+        ms = np.zeros(4)
+        cnt = (ctypes.c_longlong * 4)()
+        _check(load_library().sadi_get_kernel_times(self._ctx, _dptr(ms), cnt))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNELS)}
 
     # -- entry points
     def first_step(self, phi1, phi2, out=None):

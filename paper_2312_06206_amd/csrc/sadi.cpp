@@ -68,6 +68,12 @@ struct sadi_ctx {
 
   std::vector<void*> allocs;
 
+  // per-kernel timing: events[5*s + k] precedes kernel k of timed step s (k = 4: end)
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  int timed_steps = 0;
+  static constexpr int kMaxTimedSteps = 8192;
+
   sadi_status alloc(void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
@@ -81,6 +87,19 @@ struct sadi_ctx {
   void release() {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
+  }
+  // event k of the current timed step (creating it on demand); null when not timing
+  hipEvent_t mark(int k) {
+    if (!timing || timed_steps >= kMaxTimedSteps) return nullptr;
+    const size_t idx = (size_t)timed_steps * 5 + k;
+    while (events.size() <= idx) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      events.push_back(e);
+    }
+    return events[idx];
   }
 };
 
@@ -178,11 +197,21 @@ sadi::StepScalars scalars(const sadi_ctx* c, bool first) {
 // mode 1 (start-up): uout = ucur + Uhat with phi2
 sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double* uprev, const double* phi2,
                          double* uout) {
+  auto mark = [&](int k) {
+    hipEvent_t e = c->mark(k);
+    if (e) (void)hipEventRecord(e, c->stream);
+  };
+  mark(0);
   dispatch_m<RowsFwd>(c->m, c, ucur);
+  mark(1);
   dispatch_m<ColsConv>(c->m, c);
+  mark(2);
   const sadi::StepScalars sc = scalars(c, mode == 1);
   dispatch_m<RowsRhs>(c->m, c, mode, ucur, phi2, c->X, c->ldX, sc);
+  mark(3);
   dispatch_m<ColsGS>(c->m, c, mode, ucur, uprev, uout);
+  mark(4);
+  if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
   return check_launch();
 }
 
@@ -395,6 +424,31 @@ sadi_status sadi_apply_lh(sadi_ctx* c, const double* u, double* out) {
   sc.sigma = c->h_alpha;
   dispatch_m<RowsRhs>(c->m, c, 2, u, (const double*)nullptr, out, c->n, sc);
   return check_launch();
+}
+
+sadi_status sadi_set_kernel_timing(sadi_ctx* c, int enable) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  c->timing = enable != 0;
+  c->timed_steps = 0;
+  return SADI_OK;
+}
+
+sadi_status sadi_get_kernel_times(sadi_ctx* c, double* ms, long long* count) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (!ms || !count) return fail(SADI_E_INVALID, "NULL output");
+  SADI_HIP(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  for (int s = 0; s < c->timed_steps; ++s)
+    for (int k = 0; k < 4; ++k) {
+      float t = 0.0f;
+      SADI_HIP(hipEventElapsedTime(&t, c->events[(size_t)s * 5 + k], c->events[(size_t)s * 5 + k + 1]));
+      ms[k] += t;
+      count[k] += 1;
+    }
+  return SADI_OK;
 }
 
 sadi_status sadi_get_info(const sadi_ctx* c, int* n, int* m, long long* bytes) {
