@@ -147,26 +147,29 @@ template <int N, int DIR, typename V> __device__ __forceinline__ void dft(V* a) 
   else static_assert(N == 16, "radix not supported");
 }
 
-// a[k] *= w^k, k = 0..N-1, with w^k formed by short product chains (depth <= 4)
+// a[k] *= w^k, k = 0..N-1.  Powers by a running product restarted from w^4 every four
+// steps (product depth <= 6, few live registers).
 template <int N, typename V> __device__ __forceinline__ void twiddle_powers(V* a, V w) {
   if constexpr (N == 1) return;
-  V w2 = cmul(w, w);
-  a[1] = cmul(a[1], w);
+  V p = w;
+  a[1] = cmul(a[1], p);
   if constexpr (N >= 4) {
-    V w3 = cmul(w2, w);
+    V w2 = cmul(w, w);
     a[2] = cmul(a[2], w2);
-    a[3] = cmul(a[3], w3);
+    a[3] = cmul(a[3], cmul(w2, w));
     if constexpr (N >= 8) {
-      V w4 = cmul(w2, w2);
+      const V w4 = cmul(w2, w2);
+      V g = w4;
 #pragma unroll
-      for (int g = 1; g < N / 4; ++g) {
-        V wg = w4;
-        if (g == 2) wg = cmul(w4, w4);
-        if (g == 3) wg = cmul(cmul(w4, w4), w4);
-        a[4 * g] = cmul(a[4 * g], wg);
-        a[4 * g + 1] = cmul(a[4 * g + 1], cmul(wg, w));
-        a[4 * g + 2] = cmul(a[4 * g + 2], cmul(wg, w2));
-        a[4 * g + 3] = cmul(a[4 * g + 3], cmul(wg, w3));
+      for (int q = 1; q < N / 4; ++q) {
+        if (q > 1) g = cmul(g, w4);
+        a[4 * q] = cmul(a[4 * q], g);
+        V r = cmul(g, w);
+        a[4 * q + 1] = cmul(a[4 * q + 1], r);
+        r = cmul(g, w2);
+        a[4 * q + 2] = cmul(a[4 * q + 2], r);
+        r = cmul(r, w);
+        a[4 * q + 3] = cmul(a[4 * q + 3], r);
       }
     }
   }
@@ -210,6 +213,8 @@ struct Line {
   static constexpr int T = M / E;          // threads per line
   static constexpr int NT = T * LPW;       // threads per workgroup
   static constexpr int PAD = 1;
+  static constexpr bool LINE_FAST_ = LINE_FAST;
+  static constexpr int LPW_ = LPW;
   static_assert((M + E * PAD) % 2 == 0, "region must hold whole complex values");
   static constexpr int REGION = M + E * PAD;      // elements per line in the exchange
   static constexpr int LDS_ELEMS = REGION * LPW;

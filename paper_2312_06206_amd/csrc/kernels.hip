@@ -37,42 +37,96 @@ __device__ __forceinline__ int xcd_group(int nblocks_used) {
 }
 
 // ----------------------------------------------------------------------------------
+// Line access in canonical layout for lines of length N = M - 1 (stride `st` elements):
+// slot m holds index k = t + T m; k = N (t = T-1, m = E-1) is the only index outside a
+// line, and M-1-k = N only for t = 0, m = 0.
+// d[m] = (v[k], v[M-1-k]) with v[N] = 0: the Gohberg-Semencul input v + i J v.
+template <int M, int E, int T>
+__device__ __forceinline__ void load_line_pair(V* d, const double* __restrict__ v, int st, int t) {
+  // k = t + T m < N except m = E-1, t = T-1; M-1-k = (T-1-t) + T (E-1-m) < N except m = 0, t = 0
+  const int kf = t * st, kr = (T - 1 - t) * st;
+#pragma unroll
+  for (int g = 0; g < E; g += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      const double a = (m == E - 1) ? (v + T * m * st)[min(t, T - 2) * st] : (v + T * m * st)[kf];
+      const double b = (m == 0) ? (v + T * (E - 1) * st)[min(T - 1 - t, T - 2) * st]
+                                : (v + T * (E - 1 - m) * st)[kr];
+      d[m].x = (m == E - 1 && t == T - 1) ? 0.0 : a;
+      d[m].y = (m == 0 && t == 0) ? 0.0 : b;
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
+template <int M, int E, int T>
+__device__ __forceinline__ void store_line(const V* d, double* __restrict__ v, int st, int t) {
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    if (m < E - 1 || t < T - 1) (v + T * m * st)[t * st] = d[m].x;
+}
+
+// ----------------------------------------------------------------------------------
 // Gohberg-Semencul solve on a line in canonical layout.  On entry slot m holds
 // v1[k] = v[k] + i v[M-1-k], k = t + T m (v the bordered right-hand side, v[M-1] = 0).
 // On exit slot m holds w[k] = (H_M^-1 [v;0])[k] minus the bordering correction,
 // i.e. (H_N^-1 v)[k] for k < N.  lam_s carries the 1/(2 p_1) and both 1/M.
+// d[m] *= tab[t + T m] (CONJ: times the conjugate), loads issued in groups of four so
+// that at most four table values are live at once.
+template <int E, int T, bool CONJ>
+__device__ __forceinline__ void pointwise(V* d, const V* __restrict__ tab, int t) {
+#pragma unroll
+  for (int g = 0; g < E; g += 4) {
+    V w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = (tab + T * (g + j))[t];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d[g + j] = CONJ ? cmulc(d[g + j], w[j]) : cmul(d[g + j], w[j]);
+    asm volatile("" ::: "memory");
+  }
+}
+
 template <class LineT>
 __device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const FFTTables<double>& tab,
                                          const GSTables64& gs) {
   constexpr int M = LineT::M, E = LineT::E, T = LineT::T;
   const int t = L.t;
   // v2 = Q^H ifft(lam_s o fft(Q v1))
-#pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = cmul(d[m], gs.q[t + T * m]);
+  pointwise<E, T, false>(d, gs.q, t);
   L.template transform<-1>(d, lds, tab);
-#pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = cmul(d[m], gs.lam_s[t + T * m]);
+  pointwise<E, T, false>(d, gs.lam_s, t);
   L.template transform<+1>(d, lds, tab);
-#pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = cmulc(d[m], gs.q[t + T * m]);
+  pointwise<E, T, true>(d, gs.q, t);
   // v3 = ifft(lam_c o fft(v2))
   L.template transform<-1>(d, lds, tab);
-#pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = cmul(d[m], gs.lam_c[t + T * m]);
+  pointwise<E, T, false>(d, gs.lam_c, t);
   L.template transform<+1>(d, lds, tab);
   // w = Re(v3) + J Im(v3); bordering correction w[:N] - f * w[N]
   double* buf = reinterpret_cast<double*>(lds);
+  constexpr int SC = LineT::LINE_FAST_ ? LineT::LPW_ : 1;
+  const int wb = L.lds_index(t), rb = L.lds_index(T - 1 - t);
 #pragma unroll
-  for (int m = 0; m < E; ++m) L.put_real(buf, t + T * m, d[m].y);
+  for (int m = 0; m < E; ++m) buf[wb + SC * T * m] = d[m].y;
   if (t == T - 1) L.put_real(buf, M, d[E - 1].x);   // Re v3[M-1]
   __syncthreads();
   const double wN = L.get_real(buf, M) + L.get_real(buf, 0);
+  // (J Im v3)[k] = Im v3[M-1-k], M-1-k = (T-1-t) + T (E-1-m)
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = t + T * m;
-    const double w = d[m].x + L.get_real(buf, M - 1 - k);
-    const double f = (k < M - 1) ? gs.f[k] : 0.0;
-    d[m].x = w - f * wN;
+  for (int g = 0; g < E; g += 4) {
+    double f[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      f[j] = (gs.f + T * m)[m == E - 1 ? min(t, T - 2) : t];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      const double fm = (m == E - 1 && t == T - 1) ? 0.0 : f[j];   // k = N: no correction
+      d[m].x = d[m].x + buf[rb + SC * T * (E - 1 - m)] - fm * wN;
+    }
+    asm volatile("" ::: "memory");
   }
   __syncthreads();
 }
@@ -80,7 +134,7 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const 
 // ----------------------------------------------------------------------------------
 // rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M
 template <int M>
-__global__ void __launch_bounds__(RowCfg<M>::NT)
+__global__ void __launch_bounds__(RowCfg<M>::NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 rows_fwd_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int n,
                 FFTTables<double> tab, const V* __restrict__ root2M) {
   using L_t = typename RowCfg<M>::Line;
@@ -91,13 +145,18 @@ rows_fwd_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int ld
   const bool live = y < n;
   const double* row = u + (size_t)(live ? y : 0) * ldu;
   V d[E];
-  // z[m] = x[2m] + i x[2m+1]; x[n] = 0 for n >= N
+  // z[m] = x[2m] + i x[2m+1], x[n] = 0 for n >= N = M - 1: slots c >= E/2 are zero and
+  // only x[M-1] (odd part of the last nonzero z) falls outside the row
 #pragma unroll
   for (int c = 0; c < E; ++c) {
-    const int m = L.t + T * c;
-    const int n0 = 2 * m, n1 = 2 * m + 1;
-    d[c].x = (live && n0 < n) ? row[n0] : 0.0;
-    d[c].y = (live && n1 < n) ? row[n1] : 0.0;
+    if (c < E / 2) {
+      const int m = L.t + T * c;
+      d[c].x = row[2 * m];
+      const double odd = row[min(2 * m + 1, M - 2)];
+      d[c].y = (c == E / 2 - 1 && L.t == T - 1) ? 0.0 : odd;
+    } else {
+      d[c] = V{0.0, 0.0};
+    }
   }
   L.template transform<-1>(d, smem, tab);
   // pair Z[k] with Z[M-k] through a half-length complex buffer in two rounds: slots
@@ -164,41 +223,69 @@ cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ 
   const bool live = col <= M;   // M + 1 columns
   const int colc = live ? col : M;
   V d[E];
+  const int t = L.t;
+  // Addresses: uniform base (per slot) + one per-lane offset.
+  // y = N (m = E-1, t = T-1) is the zero padding row; odd lines take W_P^y c[y]
+  const int so = t * lds_ + colc;
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int y = L.t + T * m;
-    V c = (y < n) ? S[(size_t)y * lds_ + colc] : V{0.0, 0.0};
-    if (odd) c = cmul(c, root2M[y]);                 // W_P^y
-    d[m] = c;
+  for (int g = 0; g < E; g += 4) {
+    V c[4], w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      c[j] = (m == E - 1) ? (S + T * m * lds_)[min(t, T - 2) * lds_ + colc] : (S + T * m * lds_)[so];
+      w[j] = (root2M + T * m)[t];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      if (m == E - 1 && t == T - 1) c[j] = V{0.0, 0.0};
+      d[m] = odd ? cmul(c[j], w[j]) : c[j];
+    }
+    asm volatile("" ::: "memory");
   }
   L.template transform<-1>(d, smem, tab);
-  // eigenvalues of the embedding, row kx: [Lam_e(0..M/2), Lam_o(0..M/2-1)] (even, mirrored)
-  const double* lr = lam + (size_t)colc * ldlam;
+  // eigenvalues of the embedding, row kx: [Lam_e(0..M/2), Lam_o(0..M/2-1)] (even in ky):
+  //   k < M/2 : even Lam_e[k],       odd Lam_o[k]           -> k + odd (M/2 + 1)
+  //   k >= M/2: even Lam_e[M-k],     odd Lam_o[M-1-k]       -> M - k + odd (M/2)
+  const int lo = colc * ldlam + t + odd * (M / 2 + 1);
+  const int hi = colc * ldlam - t + odd * (M / 2);
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = L.t + T * m;
-    const double s = odd ? lr[M / 2 + 1 + min(k, M - 1 - k)] : lr[min(k, M - k)];
-    d[m] = cscale(d[m], s);
+  for (int g = 0; g < E; g += 4) {
+    double sv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      sv[j] = (m < E / 2) ? (lam + T * m)[lo] : (lam + (M - T * m))[hi];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d[g + j] = cscale(d[g + j], sv[j]);
+    asm volatile("" ::: "memory");
   }
   L.template transform<+1>(d, smem, tab);
   // combine: out[y] = even[y] + W_P^{-y} odd[y]; the two lines of a column share
   // their exchange space as one complex buffer (complex index y * CPW + column slot)
   V* xb = reinterpret_cast<V*>(smem);
   static_assert(Cfg::LINE_FAST, "column pairing assumes interleaved lines");
-  const int slot = L.line / 2;
-  if (odd) {
+  const int xo = t * CPW + L.line / 2;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int y = L.t + T * m;
-      xb[y * CPW + slot] = cmulc(d[m], root2M[y]);
+  for (int g = 0; g < E; g += 4) {
+    V w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = (root2M + T * (g + j))[t];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const V v = cmulc(d[g + j], w[j]);
+      if (odd) (xb + T * CPW * (g + j))[xo] = v;
     }
+    asm volatile("" ::: "memory");
   }
   __syncthreads();
   if (!odd && live) {
+    const int wo = t * lds_ + col;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int y = L.t + T * m;
-      if (y < n) S[(size_t)y * lds_ + col] = cadd(d[m], xb[y * CPW + slot]);
+      if (m < E - 1 || t < T - 1) (S + T * m * lds_)[wo] = cadd(d[m], (xb + T * CPW * m)[xo]);
     }
   }
 }
@@ -208,7 +295,7 @@ cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ 
 // gamma g(u) [+ tau phi2]; X = H^-1 B on the x-line.  MODE: 0 = step (n >= 1),
 // 1 = start-up step (n = 0, adds tau phi2), 2 = L_h only (X = sigma x, no solve).
 template <int M, int MODE>
-__global__ void __launch_bounds__(RowCfg<M>::NT)
+__global__ void __launch_bounds__(RowCfg<M>::NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
@@ -221,19 +308,32 @@ rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__
   const int yy = live ? y : 0;
   const V* srow = S + (size_t)yy * lds_;
   V d[E];
+  const int t = L.t;
   // c2r pre-processing: Z[k] = FE[k] + i FO[k], FE = (X[k] + conj X[M-k])/2,
-  // FO = W_P^{-k} (X[k] - conj X[M-k])/2 ; the 1/2 is folded into Lambda
+  // FO = W_P^{-k} (X[k] - conj X[M-k])/2 ; the 1/2 is folded into Lambda.
+  // X[M-k] with M-k = (M - T m) - t: uniform base minus the lane index
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = L.t + T * m;
-    const V xk = srow[k];
-    const V xm = cconj(srow[M - k]);
-    const V fe = cadd(xk, xm);
-    const V fo = cmulc(csub(xk, xm), root2M[k]);
-    d[m] = V{fe.x - fo.y, fe.y + fo.x};
+  for (int g = 0; g < E; g += 4) {
+    V xk[4], xm[4], w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = g + j;
+      xk[j] = (srow + T * m)[t];
+      xm[j] = (srow + (M - T * m))[-t];
+      w[j] = (root2M + T * m)[t];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const V c = cconj(xm[j]);
+      const V fe = cadd(xk[j], c);
+      const V fo = cmulc(csub(xk[j], c), w[j]);
+      d[g + j] = V{fe.x - fo.y, fe.y + fo.x};
+    }
+    asm volatile("" ::: "memory");
   }
   L.template transform<+1>(d, smem, tab);
-  // slot m holds z[j], j = t + T m: x[2j] = Re, x[2j+1] = Im
+  // slot m holds z[j], j = t + T m: x[2j] = Re, x[2j+1] = Im; only j < M/2 (slots
+  // m < E/2) carry x[i] with i < M, and x[M-1] (j = M/2-1, odd part) is outside the grid
   const double* urow = u + (size_t)yy * ldu;
   double* buf = reinterpret_cast<double*>(smem);
   if constexpr (MODE == 2) {
@@ -242,46 +342,39 @@ rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__
 #pragma unroll
       for (int m = 0; m < E / 2; ++m) {
         const int j = L.t + T * m;
-        if (2 * j < n) xo[2 * j] = sc.sigma * d[m].x;
-        if (2 * j + 1 < n) xo[2 * j + 1] = sc.sigma * d[m].y;
+        xo[2 * j] = sc.sigma * d[m].x;
+        if (m < E / 2 - 1 || L.t < T - 1) xo[2 * j + 1] = sc.sigma * d[m].y;
       }
     }
     return;
   } else {
     const double* prow = (MODE == 1) ? phi2 + (size_t)yy * ldu : nullptr;
+    // x[2j + h], j = t + T m: uniform base 2 T m, lane offset 2 t + h; x[N] (the last odd
+    // value of slot E/2-1 of lane T-1) is outside the grid and B[N] = 0
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int j = L.t + T * m;
+    for (int m = 0; m < E / 2; ++m) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int idx = 2 * j + h;
-        if (idx < M) {
-          double b = 0.0;
-          if (idx < n) {
-            const double xv = h ? d[m].y : d[m].x;
-            const double uv = urow[idx];
-            b = sc.sigma * xv + sc.gamma * g_of(uv, sc.gkind, sc.gparam);
-            if constexpr (MODE == 1) b += sc.tau * prow[idx];
-          }
-          L.put_real(buf, idx, b);
-        }
+        const bool last = (h == 1 && m == E / 2 - 1);
+        const int lane_off = last ? min(2 * t + 1, 2 * T - 2) : 2 * t + h;
+        const double uv = (urow + 2 * T * m)[lane_off];
+        const double xv = h ? d[m].y : d[m].x;
+        double b = sc.sigma * xv + sc.gamma * g_of(uv, sc.gkind, sc.gparam);
+        if constexpr (MODE == 1) b += sc.tau * (prow + 2 * T * m)[lane_off];
+        L.put_real(buf, 2 * (t + T * m) + h, (last && t == T - 1) ? 0.0 : b);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int k = L.t + T * m;
-      d[m] = V{L.get_real(buf, k), L.get_real(buf, M - 1 - k)};
-    }
+    for (int m = 0; m < E; ++m)   // v[k], v[M-1-k] with M-1-k = (T-1-t) + T (E-1-m)
+      d[m] = V{L.get_real(buf, t + T * m), L.get_real(buf, (T - 1 - t) + T * (E - 1 - m))};
     __syncthreads();
     gs_solve(L, d, smem, tab, gs);
     if (live) {
+      // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
       double* xo = X + (size_t)y * ldx;
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int k = L.t + T * m;
-        if (k < n) xo[k] = d[m].x;
-      }
+      for (int m = 0; m < E; ++m) (xo + T * m)[t] = d[m].x;
     }
   }
 }
@@ -289,7 +382,7 @@ rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__
 // ----------------------------------------------------------------------------------
 // rows_gs: in-place H^-1 on nlines lines of length N (stride ld).
 template <int M>
-__global__ void __launch_bounds__(RowCfg<M>::NT)
+__global__ void __launch_bounds__(RowCfg<M>::NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<double> tab, GSTables64 gs) {
   using L_t = typename RowCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
@@ -299,21 +392,9 @@ rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<
   const bool live = y < nlines;
   double* row = lines + (size_t)(live ? y : 0) * ld;
   V d[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = L.t + T * m;
-    const int kr = M - 1 - k;
-    d[m].x = (live && k < n) ? row[k] : 0.0;
-    d[m].y = (live && kr < n) ? row[kr] : 0.0;
-  }
+  load_line_pair<M, E, T>(d, row, 1, L.t);
   gs_solve(L, d, smem, tab, gs);
-  if (live) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int k = L.t + T * m;
-      if (k < n) row[k] = d[m].x;
-    }
-  }
+  if (live) store_line<M, E, T>(d, row, 1, L.t);
 }
 
 // ----------------------------------------------------------------------------------
@@ -334,20 +415,14 @@ cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const 
   const bool live = col < n;
   const int cc = live ? col : 0;
   V d[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = L.t + T * m;
-    const int kr = M - 1 - k;
-    d[m].x = (live && k < n) ? X[(size_t)k * ldx + cc] : 0.0;
-    d[m].y = (live && kr < n) ? X[(size_t)kr * ldx + cc] : 0.0;
-  }
+  load_line_pair<M, E, T>(d, X + cc, ldx, L.t);
   gs_solve(L, d, smem, tab, gs);
   if (live) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int k = L.t + T * m;
-      if (k < n) {
-        const size_t o = (size_t)k * ldu + col;
+      if (m < E - 1 || L.t < T - 1) {          // k < N
+        const int o = k * ldu + col;
         const double uc = ucur[o];
         if constexpr (MODE == 0) uout[o] = 2.0 * uc - uprev[o] + d[m].x;
         else uout[o] = uc + d[m].x;
