@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP32 / FP32+refine runs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -127,6 +128,28 @@ def main():
     s.set_kernel_timing(False)
     finite = bool(torch.isfinite(u1).all().item())
 
+    # precision variants on the same workload: speed, and the final state's difference from
+    # the FP64 path (which matches the FP64 oracle to ~1e-12 per step)
+    variants = {}
+    if not args.no_variants:
+        ref_final = u1.clone()
+        for prec in ("fp32_refine", "fp32"):
+            s.set_options(wl.g, 0.0, prec)
+            v0 = torch.from_numpy(np.ascontiguousarray(wl.phi1().T)).to(dev)
+            v1 = s.first_step(v0, phi2)
+            if args.warmup:
+                s.run(v0, v1, args.warmup + (args.warmup % 2))
+            torch.cuda.synchronize()
+            t0v = time.perf_counter()
+            s.run(v0, v1, steps)
+            torch.cuda.synchronize()
+            dtv = time.perf_counter() - t0v
+            err = float((v1 - ref_final).abs().max() / ref_final.abs().max())
+            variants[prec] = {"ms_per_step": 1e3 * dtv / steps, "value": wl.n * wl.n * steps / dtv,
+                              "speedup_vs_fp64": dt / dtv, "rel_err_vs_fp64_path": err,
+                              "steps": steps + args.warmup + (args.warmup % 2) + 1}
+        s.set_options(wl.g, 0.0, "fp64")
+
     n = wl.n
     value = n * n * steps / dt
     ms_per_step = 1e3 * dt / steps
@@ -161,6 +184,7 @@ def main():
         "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
         "setup_s": setup_s,
         "finite": finite,
+        "precision_variants": variants,
     }
     s.close()
     if not args.no_cpu_baseline:

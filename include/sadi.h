@@ -82,7 +82,10 @@ sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const doub
 sadi_status sadi_setup_with_coeffs(double alpha, double kappa, int n, double tau, const double* domain,
                                    const double* a1, const double* a2, sadi_ctx** out);
 
-/* Select g and the line-solve arithmetic (takes effect at the next call). */
+/* Select g and the line-solve arithmetic (takes effect at the next call).  With
+ * SADI_FP32_REFINE every line solve is x0 = GS32(v), r = v - H x0 in float64 (product with
+ * H through a 2(N+1)-point circulant embedding), x = x0 + GS32(r); SADI_FP32 stops at x0.
+ * Both apply to sadi_first_step / sadi_step / sadi_run and sadi_toeplitz_solve. */
 sadi_status sadi_set_options(sadi_ctx* ctx, sadi_g_kind g, double g_param, sadi_precision prec);
 
 /* Run subsequent calls on this HIP stream (a hipStream_t, e.g. torch's current

@@ -214,6 +214,7 @@ struct Line {
   static constexpr int NT = T * LPW;       // threads per workgroup
   static constexpr int PAD = 1;
   static constexpr bool LINE_FAST_ = LINE_FAST;
+  using Real = R;
   static constexpr int LPW_ = LPW;
   static_assert((M + E * PAD) % 2 == 0, "region must hold whole complex values");
   static constexpr int REGION = M + E * PAD;      // elements per line in the exchange

@@ -26,6 +26,11 @@ namespace sadi {
 
 using V = double2;
 
+// at least 4 waves per SIMD: <= 128 VGPRs, several workgroups per CU to overlap barriers
+#define SADI_OCC4 __attribute__((amdgpu_waves_per_eu(4, 8)))
+// mixed-precision kernels hold more per-line state: 2 waves per SIMD, <= 256 VGPRs
+#define SADI_OCC2 __attribute__((amdgpu_waves_per_eu(1, 8)))
+
 // ----------------------------------------------------------------------------------
 // XCD-aware block order for column kernels: consecutive dispatch slots go to the 8
 // XCDs round robin, so give the blocks of one XCD adjacent column groups (their row
@@ -46,17 +51,14 @@ __device__ __forceinline__ void load_line_pair(V* d, const double* __restrict__ 
   // k = t + T m < N except m = E-1, t = T-1; M-1-k = (T-1-t) + T (E-1-m) < N except m = 0, t = 0
   const int kf = t * st, kr = (T - 1 - t) * st;
 #pragma unroll
-  for (int g = 0; g < E; g += 4) {
+  for (int m = 0; m < E; ++m) {
+    d[m].x = (m == E - 1) ? (v + T * m * st)[min(t, T - 2) * st] : (v + T * m * st)[kf];
+    d[m].y = (m == 0) ? (v + T * (E - 1) * st)[min(T - 1 - t, T - 2) * st] : (v + T * (E - 1 - m) * st)[kr];
+  }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = g + j;
-      const double a = (m == E - 1) ? (v + T * m * st)[min(t, T - 2) * st] : (v + T * m * st)[kf];
-      const double b = (m == 0) ? (v + T * (E - 1) * st)[min(T - 1 - t, T - 2) * st]
-                                : (v + T * (E - 1 - m) * st)[kr];
-      d[m].x = (m == E - 1 && t == T - 1) ? 0.0 : a;
-      d[m].y = (m == 0 && t == 0) ? 0.0 : b;
-    }
-    asm volatile("" ::: "memory");
+  for (int m = 0; m < E; ++m) {
+    if (m == E - 1 && t == T - 1) d[m].x = 0.0;
+    if (m == 0 && t == 0) d[m].y = 0.0;
   }
 }
 
@@ -74,22 +76,45 @@ __device__ __forceinline__ void store_line(const V* d, double* __restrict__ v, i
 // i.e. (H_N^-1 v)[k] for k < N.  lam_s carries the 1/(2 p_1) and both 1/M.
 // d[m] *= tab[t + T m] (CONJ: times the conjugate), loads issued in groups of four so
 // that at most four table values are live at once.
-template <int E, int T, bool CONJ>
-__device__ __forceinline__ void pointwise(V* d, const V* __restrict__ tab, int t) {
+template <int E, int T, bool CONJ, typename VV>
+__device__ __forceinline__ void pointwise(VV* d, const VV* __restrict__ tab, int t) {
+  // groups of four, the next group's loads issued before the current group is used
+  VV w[4], nx[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w[j] = (tab + T * j)[t];
 #pragma unroll
   for (int g = 0; g < E; g += 4) {
-    V w[4];
+    if (g + 4 < E) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) nx[j] = (tab + T * (g + 4 + j))[t];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d[g + j] = CONJ ? cmulc(d[g + j], w[j]) : cmul(d[g + j], w[j]);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = nx[j];
+  }
+}
+
+// d[m] *= tab[t + T m] for a real table
+template <int E, int T, typename VV, typename R>
+__device__ __forceinline__ void pointwise_real(VV* d, const R* __restrict__ tab, int t) {
+#pragma unroll
+  for (int g = 0; g < E; g += 4) {
+    R w[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) w[j] = (tab + T * (g + j))[t];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) d[g + j] = CONJ ? cmulc(d[g + j], w[j]) : cmul(d[g + j], w[j]);
+    for (int j = 0; j < 4; ++j) d[g + j] = cscale(d[g + j], w[j]);
     asm volatile("" ::: "memory");
   }
 }
 
 template <class LineT>
-__device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const FFTTables<double>& tab,
-                                         const GSTables64& gs) {
+__device__ __forceinline__ void gs_solve(const LineT& L, V2<typename LineT::Real>* d, void* lds,
+                                         const FFTTables<typename LineT::Real>& tab,
+                                         const GSTables<typename LineT::Real>& gs) {
+  using R = typename LineT::Real;
   constexpr int M = LineT::M, E = LineT::E, T = LineT::T;
   const int t = L.t;
   // v2 = Q^H ifft(lam_s o fft(Q v1))
@@ -103,18 +128,18 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const 
   pointwise<E, T, false>(d, gs.lam_c, t);
   L.template transform<+1>(d, lds, tab);
   // w = Re(v3) + J Im(v3); bordering correction w[:N] - f * w[N]
-  double* buf = reinterpret_cast<double*>(lds);
+  R* buf = reinterpret_cast<R*>(lds);
   constexpr int SC = LineT::LINE_FAST_ ? LineT::LPW_ : 1;
   const int wb = L.lds_index(t), rb = L.lds_index(T - 1 - t);
 #pragma unroll
   for (int m = 0; m < E; ++m) buf[wb + SC * T * m] = d[m].y;
   if (t == T - 1) L.put_real(buf, M, d[E - 1].x);   // Re v3[M-1]
   __syncthreads();
-  const double wN = L.get_real(buf, M) + L.get_real(buf, 0);
+  const R wN = L.get_real(buf, M) + L.get_real(buf, 0);
   // (J Im v3)[k] = Im v3[M-1-k], M-1-k = (T-1-t) + T (E-1-m)
 #pragma unroll
   for (int g = 0; g < E; g += 4) {
-    double f[4];
+    R f[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int m = g + j;
@@ -123,7 +148,7 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int m = g + j;
-      const double fm = (m == E - 1 && t == T - 1) ? 0.0 : f[j];   // k = N: no correction
+      const R fm = (m == E - 1 && t == T - 1) ? R(0) : f[j];   // k = N: no correction
       d[m].x = d[m].x + buf[rb + SC * T * (E - 1 - m)] - fm * wN;
     }
     asm volatile("" ::: "memory");
@@ -131,10 +156,83 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V* d, void* lds, const 
   __syncthreads();
 }
 
+// y[k] = (beta T(a) x)[k], k = t + T m, for a real line x (FP64): the 2M-point circulant
+// embedding split into its even and odd frequencies,
+//   y = ifft(sig_e o fft(x)) + Q^H ifft(sig_o o fft(Q x)),  Q = diag(e^{-i pi k/M}).
+template <class LineT>
+__device__ __forceinline__ void toeplitz_apply64(const LineT& L, const float* x, double* y, void* lds,
+                                                 const FFTTables<double>& tab, const ToeplitzTables64& toe,
+                                                 const double2* __restrict__ q) {
+  constexpr int E = LineT::E, T = LineT::T;
+  const int t = L.t;
+  V d[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = V{(double)x[m], 0.0};
+  L.template transform<-1>(d, lds, tab);
+  pointwise_real<E, T>(d, toe.sig_e, t);
+  L.template transform<+1>(d, lds, tab);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    y[m] = d[m].x;
+    d[m] = V{(double)x[m], 0.0};
+  }
+  pointwise<E, T, false>(d, q, t);
+  L.template transform<-1>(d, lds, tab);
+  pointwise_real<E, T>(d, toe.sig_o, t);
+  L.template transform<+1>(d, lds, tab);
+  pointwise<E, T, true>(d, q, t);
+#pragma unroll
+  for (int m = 0; m < E; ++m) y[m] += d[m].x;
+}
+
+// Mixed-precision line solve.  On entry dv[m] = (v[k], v[M-1-k]) (FP64, v[N] = 0); on exit
+// dv[m].x = x[k] with x = x0 + x1, x0 = GS32(v), x1 = GS32(v - H x0) (FP64 residual) when
+// refining, else x = x0.
+template <class Line64, class Line32>
+__device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V* dv, void* lds,
+                                            const FFTTables<double>& tab, const MixedTables& mx) {
+  constexpr int M = Line64::M, E = Line64::E, T = Line64::T;
+  const int t = L.t;
+  float2 df[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) df[m] = float2{(float)dv[m].x, (float)dv[m].y};
+  gs_solve(Lf, df, lds, mx.tab32, mx.gs32);
+  if (!mx.refine) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) dv[m].x = (double)df[m].x;
+    return;
+  }
+  float x0[E];
+  double r[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) x0[m] = df[m].x;
+  if (t == T - 1) x0[E - 1] = 0.0f;   // slot k = N holds the bordering unknown, not x
+  // r = v - x0 - beta T x0  (FP64, x0 is exactly representable), r[N] = 0
+  toeplitz_apply64(L, x0, r, lds, tab, mx.toe, mx.q64);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    r[m] = dv[m].x - (double)x0[m] - r[m];
+    if (m == E - 1 && t == T - 1) r[m] = 0.0;
+  }
+  // reversed copy of r through LDS
+  double* buf = reinterpret_cast<double*>(lds);
+#pragma unroll
+  for (int m = 0; m < E; ++m) L.put_real(buf, t + T * m, r[m]);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    df[m] = float2{(float)r[m], (float)L.get_real(buf, (T - 1 - t) + T * (E - 1 - m))};
+  __syncthreads();
+  gs_solve(Lf, df, lds, mx.tab32, mx.gs32);
+#pragma unroll
+  for (int m = 0; m < E; ++m) dv[m].x = (double)x0[m] + (double)df[m].x;
+  (void)M;
+}
+
 // ----------------------------------------------------------------------------------
 // rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M
 template <int M>
-__global__ void __launch_bounds__(RowCfg<M>::NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_fwd_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int n,
                 FFTTables<double> tab, const V* __restrict__ root2M) {
   using L_t = typename RowCfg<M>::Line;
@@ -207,7 +305,7 @@ rows_fwd_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int ld
 // into its even and odd frequencies (two length-M transforms of c and W_P^y c), each
 // handled by its own line of the workgroup (lines 2g / 2g+1 for column group g).
 template <int M>
-__global__ void __launch_bounds__(ColConvCfg<M>::NT)
+__global__ void __launch_bounds__(ColConvCfg<M>::NT) SADI_OCC4
 cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
                  FFTTables<double> tab, const V* __restrict__ root2M, int ngroups) {
   using Cfg = ColConvCfg<M>;
@@ -228,20 +326,16 @@ cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ 
   // y = N (m = E-1, t = T-1) is the zero padding row; odd lines take W_P^y c[y]
   const int so = t * lds_ + colc;
 #pragma unroll
+  for (int m = 0; m < E; ++m)
+    d[m] = (m == E - 1) ? (S + T * m * lds_)[min(t, T - 2) * lds_ + colc] : (S + T * m * lds_)[so];
+  if (t == T - 1) d[E - 1] = V{0.0, 0.0};
+#pragma unroll
   for (int g = 0; g < E; g += 4) {
-    V c[4], w[4];
+    V w[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = g + j;
-      c[j] = (m == E - 1) ? (S + T * m * lds_)[min(t, T - 2) * lds_ + colc] : (S + T * m * lds_)[so];
-      w[j] = (root2M + T * m)[t];
-    }
+    for (int j = 0; j < 4; ++j) w[j] = (root2M + T * (g + j))[t];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = g + j;
-      if (m == E - 1 && t == T - 1) c[j] = V{0.0, 0.0};
-      d[m] = odd ? cmul(c[j], w[j]) : c[j];
-    }
+    for (int j = 0; j < 4; ++j) d[g + j] = odd ? cmul(d[g + j], w[j]) : d[g + j];
     asm volatile("" ::: "memory");
   }
   L.template transform<-1>(d, smem, tab);
@@ -294,20 +388,15 @@ cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ 
 // rows_rhs_gs: x[n] = inverse rFFT_P of S row (Lambda carries 1/(P M)); B = sigma x +
 // gamma g(u) [+ tau phi2]; X = H^-1 B on the x-line.  MODE: 0 = step (n >= 1),
 // 1 = start-up step (n = 0, adds tau phi2), 2 = L_h only (X = sigma x, no solve).
-template <int M, int MODE>
-__global__ void __launch_bounds__(RowCfg<M>::NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
-rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
-                   const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
-                   StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
-  using L_t = typename RowCfg<M>::Line;
-  constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
-  const L_t L(threadIdx.x);
-  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
-  const bool live = y < n;
-  const int yy = live ? y : 0;
-  const V* srow = S + (size_t)yy * lds_;
-  V d[E];
+//
+// rhs_phase: everything before the line solve.  Returns false for MODE 2 (output written);
+// otherwise d[m] = (B[k], B[M-1-k]) with B[N] = 0.
+template <int MODE, class L_t>
+__device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const V* __restrict__ srow,
+                                          const double* __restrict__ urow, const double* __restrict__ prow,
+                                          double* __restrict__ xo, bool live, const StepScalars& sc,
+                                          const FFTTables<double>& tab, const V* __restrict__ root2M) {
+  constexpr int M = L_t::M, E = L_t::E, T = L_t::T;
   const int t = L.t;
   // c2r pre-processing: Z[k] = FE[k] + i FO[k], FE = (X[k] + conj X[M-k])/2,
   // FO = W_P^{-k} (X[k] - conj X[M-k])/2 ; the 1/2 is folded into Lambda.
@@ -334,21 +423,18 @@ rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__
   L.template transform<+1>(d, smem, tab);
   // slot m holds z[j], j = t + T m: x[2j] = Re, x[2j+1] = Im; only j < M/2 (slots
   // m < E/2) carry x[i] with i < M, and x[M-1] (j = M/2-1, odd part) is outside the grid
-  const double* urow = u + (size_t)yy * ldu;
   double* buf = reinterpret_cast<double*>(smem);
   if constexpr (MODE == 2) {
     if (live) {
-      double* xo = X + (size_t)y * ldx;
 #pragma unroll
       for (int m = 0; m < E / 2; ++m) {
-        const int j = L.t + T * m;
+        const int j = t + T * m;
         xo[2 * j] = sc.sigma * d[m].x;
-        if (m < E / 2 - 1 || L.t < T - 1) xo[2 * j + 1] = sc.sigma * d[m].y;
+        if (m < E / 2 - 1 || t < T - 1) xo[2 * j + 1] = sc.sigma * d[m].y;
       }
     }
-    return;
+    return false;
   } else {
-    const double* prow = (MODE == 1) ? phi2 + (size_t)yy * ldu : nullptr;
     // x[2j + h], j = t + T m: uniform base 2 T m, lane offset 2 t + h; x[N] (the last odd
     // value of slot E/2-1 of lane T-1) is outside the grid and B[N] = 0
 #pragma unroll
@@ -369,20 +455,66 @@ rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__
     for (int m = 0; m < E; ++m)   // v[k], v[M-1-k] with M-1-k = (T-1-t) + T (E-1-m)
       d[m] = V{L.get_real(buf, t + T * m), L.get_real(buf, (T - 1 - t) + T * (E - 1 - m))};
     __syncthreads();
-    gs_solve(L, d, smem, tab, gs);
-    if (live) {
-      // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
-      double* xo = X + (size_t)y * ldx;
+    return true;
+  }
+}
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
+                   const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
+                   StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
+  using L_t = typename RowCfg<M>::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
+  const L_t L(threadIdx.x);
+  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
+  const bool live = y < n;
+  const int yy = live ? y : 0;
+  double* xo = X + (size_t)yy * ldx;
+  V d[E];
+  if (!rhs_phase<MODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
+                       MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M))
+    return;
+  gs_solve(L, d, smem, tab, gs);
+  if (live) {
+    // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
 #pragma unroll
-      for (int m = 0; m < E; ++m) (xo + T * m)[t] = d[m].x;
-    }
+    for (int m = 0; m < E; ++m) (xo + T * m)[L.t] = d[m].x;
+  }
+}
+
+// Mixed precision variant (MODE 0 / 1): FP32 solves, optional FP64 residual correction
+template <int M, int MODE>
+__global__ void __launch_bounds__(MixRowCfg<M>::NT) SADI_OCC2
+rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
+                      const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
+                      StepScalars sc, FFTTables<double> tab, MixedTables mx, const V* __restrict__ root2M) {
+  using Cfg = MixRowCfg<M>;
+  using L_t = typename Cfg::Line;
+  using L32 = typename Cfg::Line32;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const L_t L(threadIdx.x);
+  const L32 Lf(threadIdx.x);
+  const int y = blockIdx.x * Cfg::LPW + L.line;
+  const bool live = y < n;
+  const int yy = live ? y : 0;
+  double* xo = X + (size_t)yy * ldx;
+  V d[E];
+  rhs_phase<MODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
+                  MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M);
+  mixed_solve(L, Lf, d, smem, tab, mx);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) (xo + T * m)[L.t] = d[m].x;
   }
 }
 
 // ----------------------------------------------------------------------------------
 // rows_gs: in-place H^-1 on nlines lines of length N (stride ld).
 template <int M>
-__global__ void __launch_bounds__(RowCfg<M>::NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<double> tab, GSTables64 gs) {
   using L_t = typename RowCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
@@ -401,7 +533,7 @@ rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<
 // cols_gs: y-line solves on the columns of X and the leapfrog update.
 // MODE 0: uout = 2 ucur - uprev + Uhat (uout may alias uprev); MODE 1: uout = ucur + Uhat.
 template <int M, int MODE>
-__global__ void __launch_bounds__(ColGSCfg<M>::NT)
+__global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const double* uprev,
                double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
   using Cfg = ColGSCfg<M>;
@@ -418,14 +550,72 @@ cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const 
   load_line_pair<M, E, T>(d, X + cc, ldx, L.t);
   gs_solve(L, d, smem, tab, gs);
   if (live) {
+    // k = t + T m < N except m = E-1, t = T-1 (clamped load, no store)
+    const int o = L.t * ldu + col;
+    const int oe = min(L.t, T - 2) * ldu + col;
+    double uc[E], up[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int k = L.t + T * m;
-      if (m < E - 1 || L.t < T - 1) {          // k < N
-        const int o = k * ldu + col;
-        const double uc = ucur[o];
-        if constexpr (MODE == 0) uout[o] = 2.0 * uc - uprev[o] + d[m].x;
-        else uout[o] = uc + d[m].x;
+      uc[m] = (ucur + T * m * ldu)[m == E - 1 ? oe : o];
+      if constexpr (MODE == 0) up[m] = (uprev + T * m * ldu)[m == E - 1 ? oe : o];
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if (m < E - 1 || L.t < T - 1) {
+        if constexpr (MODE == 0) (uout + T * m * ldu)[o] = 2.0 * uc[m] - up[m] + d[m].x;
+        else (uout + T * m * ldu)[o] = uc[m] + d[m].x;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// mixed-precision in-place line solves and y-sweep
+template <int M>
+__global__ void __launch_bounds__(MixRowCfg<M>::NT) SADI_OCC2
+rows_gs_mixed_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<double> tab, MixedTables mx) {
+  using Cfg = MixRowCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const L_t L(threadIdx.x);
+  const typename Cfg::Line32 Lf(threadIdx.x);
+  const int y = blockIdx.x * Cfg::LPW + L.line;
+  const bool live = y < nlines;
+  double* row = lines + (size_t)(live ? y : 0) * ld;
+  V d[E];
+  load_line_pair<M, E, T>(d, row, 1, L.t);
+  mixed_solve(L, Lf, d, smem, tab, mx);
+  if (live) store_line<M, E, T>(d, row, 1, L.t);
+}
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(MixColCfg<M>::NT) SADI_OCC2
+cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, const double* uprev,
+                     double* uout, int ldu, int n, FFTTables<double> tab, MixedTables mx, int ngroups) {
+  using Cfg = MixColCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;
+  const L_t L(threadIdx.x);
+  const typename Cfg::Line32 Lf(threadIdx.x);
+  const int col = grp * Cfg::LPW + L.line;
+  const bool live = col < n;
+  const int cc = live ? col : 0;
+  V d[E];
+  load_line_pair<M, E, T>(d, X + cc, ldx, L.t);
+  mixed_solve(L, Lf, d, smem, tab, mx);
+  if (live) {
+    const int o = L.t * ldu + col;
+    const int oe = min(L.t, T - 2) * ldu + col;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if (m < E - 1 || L.t < T - 1) {
+        const double uc = (ucur + T * m * ldu)[m == E - 1 ? oe : o];
+        if constexpr (MODE == 0) (uout + T * m * ldu)[o] = 2.0 * uc - (uprev + T * m * ldu)[o] + d[m].x;
+        else (uout + T * m * ldu)[o] = uc + d[m].x;
       }
     }
   }
@@ -486,6 +676,40 @@ void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, cons
                        ldu, n, tab, gs, ngroups);
 }
 
+template <int M>
+void launch_rows_rhs_mixed(int mode, const V* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
+                           int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const MixedTables& mx,
+                           const V* root2M, hipStream_t st) {
+  const int grid = (n + MixRowCfg<M>::LPW - 1) / MixRowCfg<M>::LPW;
+  if (mode == 0)
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+                       phi2, X, ldx, n, sc, tab, mx, root2M);
+  else
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 1>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+                       phi2, X, ldx, n, sc, tab, mx, root2M);
+}
+
+template <int M>
+void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab,
+                          const MixedTables& mx, hipStream_t st) {
+  const int grid = (nlines + MixRowCfg<M>::LPW - 1) / MixRowCfg<M>::LPW;
+  hipLaunchKernelGGL(rows_gs_mixed_kernel<M>, dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, lines, ld, nlines, n, tab,
+                     mx);
+}
+
+template <int M>
+void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
+                          int ldu, int n, const FFTTables<double>& tab, const MixedTables& mx, hipStream_t st) {
+  const int ngroups = (n + MixColCfg<M>::LPW - 1) / MixColCfg<M>::LPW;
+  const int grid = ((ngroups + 7) / 8) * 8;
+  if (mode == 0)
+    hipLaunchKernelGGL((cols_gs_mixed_kernel<M, 0>), dim3(grid), dim3(MixColCfg<M>::NT), 0, st, X, ldx, ucur, uprev,
+                       uout, ldu, n, tab, mx, ngroups);
+  else
+    hipLaunchKernelGGL((cols_gs_mixed_kernel<M, 1>), dim3(grid), dim3(MixColCfg<M>::NT), 0, st, X, ldx, ucur, uprev,
+                       uout, ldu, n, tab, mx, ngroups);
+}
+
 #define SADI_INSTANTIATE(M)                                                                                      \
   template void launch_rows_fwd<M>(const double*, int, V*, int, int, const FFTTables<double>&, const V*,         \
                                    hipStream_t);                                                                 \
@@ -497,7 +721,14 @@ void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, cons
   template void launch_rows_gs<M>(double*, int, int, int, const FFTTables<double>&, const GSTables64&,            \
                                   hipStream_t);                                                                  \
   template void launch_cols_gs<M>(int, const double*, int, const double*, const double*, double*, int, int,       \
-                                  const FFTTables<double>&, const GSTables64&, hipStream_t);
+                                  const FFTTables<double>&, const GSTables64&, hipStream_t);                     \
+  template void launch_rows_rhs_mixed<M>(int, const V*, int, const double*, int, const double*, double*, int,     \
+                                         int, const StepScalars&, const FFTTables<double>&, const MixedTables&,  \
+                                         const V*, hipStream_t);                                                 \
+  template void launch_rows_gs_mixed<M>(double*, int, int, int, const FFTTables<double>&, const MixedTables&,     \
+                                        hipStream_t);                                                            \
+  template void launch_cols_gs_mixed<M>(int, const double*, int, const double*, const double*, double*, int, int, \
+                                        const FFTTables<double>&, const MixedTables&, hipStream_t);
 
 SADI_FOR_EACH_M(SADI_INSTANTIATE)
 

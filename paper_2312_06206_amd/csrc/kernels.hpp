@@ -9,12 +9,20 @@ namespace sadi {
 // supported line lengths M = N + 1
 #define SADI_FOR_EACH_M(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
-// tables of the Gohberg-Semencul line solve (FP64)
-struct GSTables64 {
-  const double2* q;      // Q = diag(e^{-i pi k / M}), k < M
-  const double2* lam_s;  // fft(Q s) / (2 p_1 M^2)... scaled, see the host setup
-  const double2* lam_c;  // fft(c) / M
-  const double* f;       // bordering correction (J c)[k] / p_1, k < N
+// tables of the Gohberg-Semencul line solve (R = double, or float for the FP32 solves)
+template <typename R> struct GSTables {
+  const V2<R>* q;        // Q = diag(e^{-i pi k / M}), k < M
+  const V2<R>* lam_s;    // fft(Q s) / (2 p_1 M)
+  const V2<R>* lam_c;    // fft(c) / M
+  const R* f;            // bordering correction (J c)[k] / p_1, k < N
+};
+using GSTables64 = GSTables<double>;
+
+// FP64 product with beta T(a_0..a_{N-1}) (residual of the FP32 solves): eigenvalues of its
+// 2M-point circulant embedding, even and odd frequencies, times beta / (2M)
+struct ToeplitzTables64 {
+  const double* sig_e;
+  const double* sig_o;
 };
 
 // per-call scalars of the right-hand side B = sigma (L u) h^alpha + gamma g(u) [+ tau phi2]
@@ -46,10 +54,10 @@ template <int M> struct RowCfg {
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
 };
 
-// two lines (even / odd frequency halves) per column, >= 2 columns per workgroup
+// two lines (even / odd frequency halves) per column, 512 threads per workgroup
 template <int M> struct ColConvCfg {
   static constexpr int T = M / Shape<M>::E;
-  static constexpr int LPW = (1024 / T) < 4 ? 4 : 1024 / T;
+  static constexpr int LPW = (512 / T) < 2 ? 2 : 512 / T;
   static constexpr bool LINE_FAST = true;
   static constexpr int SPLIT = 2;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
@@ -57,15 +65,45 @@ template <int M> struct ColConvCfg {
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
 };
 
-// >= 4 columns per workgroup
+// adjacent columns in adjacent lanes, 512 threads per workgroup
 template <int M> struct ColGSCfg {
   static constexpr int T = M / Shape<M>::E;
-  static constexpr int LPW = (1024 / T) < 4 ? 4 : 1024 / T;
+  static constexpr int LPW = (512 / T) < 2 ? 2 : 512 / T;
   static constexpr bool LINE_FAST = true;
   static constexpr int SPLIT = 2;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
   static constexpr int NT = Line::NT;
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
+};
+
+// mixed precision (FP32 solves, optional FP64 residual correction): 1 wave per SIMD,
+// 256 threads per workgroup
+template <int M> struct MixRowCfg {
+  static constexpr int T = M / Shape<M>::E;
+  static constexpr int LPW = T >= 256 ? 1 : 256 / T;
+  static constexpr bool LINE_FAST = false;
+  using Line = sadi::Line<M, double, LPW, LINE_FAST, 2>;
+  using Line32 = sadi::Line<M, float, LPW, LINE_FAST, 1>;
+  static constexpr int NT = Line::NT;
+  static constexpr int LDS_BYTES = Line::LDS_BYTES > Line32::LDS_BYTES ? Line::LDS_BYTES : Line32::LDS_BYTES;
+};
+template <int M> struct MixColCfg {
+  static constexpr int T = M / Shape<M>::E;
+  static constexpr int LPW = T >= 256 ? 1 : 256 / T;
+  static constexpr bool LINE_FAST = true;
+  using Line = sadi::Line<M, double, LPW, LINE_FAST, 2>;
+  using Line32 = sadi::Line<M, float, LPW, LINE_FAST, 1>;
+  static constexpr int NT = Line::NT;
+  static constexpr int LDS_BYTES = Line::LDS_BYTES > Line32::LDS_BYTES ? Line::LDS_BYTES : Line32::LDS_BYTES;
+};
+
+// everything the mixed-precision line solve needs
+struct MixedTables {
+  FFTTables<float> tab32;
+  GSTables<float> gs32;
+  ToeplitzTables64 toe;
+  const double2* q64;      // e^{-i pi k / M} (FP64), k < M
+  int refine;              // 1: one FP64 residual correction
 };
 
 template <int M>
@@ -84,5 +122,15 @@ void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<do
 template <int M>
 void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                     int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
+template <int M>
+void launch_rows_rhs_mixed(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2,
+                           double* X, int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab,
+                           const MixedTables& mx, const double2* root2M, hipStream_t st);
+template <int M>
+void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab,
+                          const MixedTables& mx, hipStream_t st);
+template <int M>
+void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
+                          int ldu, int n, const FFTTables<double>& tab, const MixedTables& mx, hipStream_t st);
 
 }  // namespace sadi

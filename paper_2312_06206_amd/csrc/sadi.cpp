@@ -65,6 +65,16 @@ struct sadi_ctx {
   int ldS = 0;
   double* X = nullptr;         // N rows x ldX
   int ldX = 0;
+  // mixed precision: FP32 copies of the FFT and Gohberg-Semencul tables, FP64 eigenvalues
+  // of the 2M-circulant embedding of beta T(a) (even / odd frequencies, scaled by 1/(2M))
+  float2* rootM32 = nullptr;
+  float2* rootS32 = nullptr;
+  float2* q32 = nullptr;
+  float2* lam_s32 = nullptr;
+  float2* lam_c32 = nullptr;
+  float* f32 = nullptr;
+  double* sig_e = nullptr;
+  double* sig_o = nullptr;
 
   std::vector<void*> allocs;
 
@@ -175,6 +185,33 @@ template <int M> struct RowsGS {
   }
 };
 
+sadi::MixedTables mixed_tables(const sadi_ctx* c) {
+  sadi::MixedTables mx{};
+  mx.tab32 = sadi::FFTTables<float>{c->rootM32, c->rootS32};
+  mx.gs32 = sadi::GSTables<float>{c->q32, c->lam_s32, c->lam_c32, c->f32};
+  mx.toe = sadi::ToeplitzTables64{c->sig_e, c->sig_o};
+  mx.q64 = c->root2M;
+  mx.refine = c->prec == SADI_FP32_REFINE ? 1 : 0;
+  return mx;
+}
+template <int M> struct RowsRhsMixed {
+  static void run(const sadi_ctx* c, int mode, const double* u, const double* phi2, const sadi::StepScalars& sc) {
+    sadi::launch_rows_rhs_mixed<M>(mode, c->S, c->ldS, u, c->n, phi2, c->X, c->ldX, c->n, sc, tables(c),
+                                   mixed_tables(c), c->root2M, c->stream);
+  }
+};
+template <int M> struct ColsGSMixed {
+  static void run(const sadi_ctx* c, int mode, const double* ucur, const double* uprev, double* uout) {
+    sadi::launch_cols_gs_mixed<M>(mode, c->X, c->ldX, ucur, uprev, uout, c->n, c->n, tables(c), mixed_tables(c),
+                                  c->stream);
+  }
+};
+template <int M> struct RowsGSMixed {
+  static void run(const sadi_ctx* c, double* lines, int ld, int nlines) {
+    sadi::launch_rows_gs_mixed<M>(lines, ld, nlines, c->n, tables(c), mixed_tables(c), c->stream);
+  }
+};
+
 sadi_status check_launch() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -207,9 +244,15 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
   dispatch_m<ColsConv>(c->m, c);
   mark(2);
   const sadi::StepScalars sc = scalars(c, mode == 1);
-  dispatch_m<RowsRhs>(c->m, c, mode, ucur, phi2, c->X, c->ldX, sc);
+  if (c->prec == SADI_FP64)
+    dispatch_m<RowsRhs>(c->m, c, mode, ucur, phi2, c->X, c->ldX, sc);
+  else
+    dispatch_m<RowsRhsMixed>(c->m, c, mode, ucur, phi2, sc);
   mark(3);
-  dispatch_m<ColsGS>(c->m, c, mode, ucur, uprev, uout);
+  if (c->prec == SADI_FP64)
+    dispatch_m<ColsGS>(c->m, c, mode, ucur, uprev, uout);
+  else
+    dispatch_m<ColsGSMixed>(c->m, c, mode, ucur, uprev, uout);
   mark(4);
   if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
   return check_launch();
@@ -281,6 +324,35 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   std::vector<double> hlam((size_t)(m + 1) * c->ldlam, 0.0);
   sadi::bccb_eigenvalues(a2, n, hlam.data(), c->ldlam);
 
+  // ---- mixed precision tables
+  std::vector<float2> hrootM32(sh.T), hrootS32(sh.E), hq32(m), hls32(m), hlc32(m);
+  std::vector<float> hf32(n);
+  for (int j = 0; j < sh.T; ++j) hrootM32[j] = make_float2((float)hrootM[j].x, (float)hrootM[j].y);
+  for (int j = 0; j < sh.E; ++j) hrootS32[j] = make_float2((float)hrootS[j].x, (float)hrootS[j].y);
+  for (int k = 0; k < m; ++k) {
+    hq32[k] = make_float2((float)hroot2M[k].x, (float)hroot2M[k].y);
+    hls32[k] = make_float2((float)hls[k].x, (float)hls[k].y);
+    hlc32[k] = make_float2((float)hlc[k].x, (float)hlc[k].y);
+  }
+  for (int k = 0; k < n; ++k) hf32[k] = (float)gsd.f[k];
+  // beta T(a_0..a_{N-1}) embedded in a circulant of size P = 2M (first column a_0..a_{N-1},
+  // three zeros, a_{N-1}..a_1); its eigenvalues split into even / odd frequencies
+  std::vector<double> hsig_e(m), hsig_o(m);
+  {
+    const int p = 2 * m;
+    std::vector<sadi::cld> cemb(p, sadi::cld(0, 0));
+    for (int j = 0; j < n; ++j) {
+      cemb[j] = a1[j];
+      if (j > 0) cemb[p - j] = a1[j];
+    }
+    sadi::fft_inplace(cemb, -1);
+    const long double sc = (long double)c->beta / p;
+    for (int k = 0; k < m; ++k) {
+      hsig_e[k] = (double)(cemb[2 * k].real() * sc);
+      hsig_o[k] = (double)(cemb[2 * k + 1].real() * sc);
+    }
+  }
+
   // ---- device allocations
   c->ldS = m + 8;           // complex elements per row of the half spectrum (>= M+1)
   c->ldX = m;
@@ -294,6 +366,14 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)n * c->ldS)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)n * c->ldX)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->rootM32, sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->rootS32, sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->q32, sizeof(float2) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->lam_s32, sizeof(float2) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->lam_c32, sizeof(float2) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->f32, sizeof(float) * n)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->sig_e, sizeof(double) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->sig_o, sizeof(double) * m)) != SADI_OK) return bail(st);
 
   auto up = [&](void* dst, const void* src, size_t bytes) -> sadi_status {
     hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -307,6 +387,14 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->lam_c, hlc.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->f, gsd.f.data(), sizeof(double) * n)) != SADI_OK) return bail(st);
   if ((st = up(c->lam2d, hlam.data(), sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
+  if ((st = up(c->rootM32, hrootM32.data(), sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
+  if ((st = up(c->rootS32, hrootS32.data(), sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
+  if ((st = up(c->q32, hq32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->lam_s32, hls32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->lam_c32, hlc32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->f32, hf32.data(), sizeof(float) * n)) != SADI_OK) return bail(st);
+  if ((st = up(c->sig_e, hsig_e.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
+  if ((st = up(c->sig_o, hsig_o.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
   *out = c;
   return SADI_OK;
 }
@@ -355,7 +443,6 @@ sadi_status sadi_set_options(sadi_ctx* c, sadi_g_kind g, double g_param, sadi_pr
   if ((int)g < 0 || (int)g > 3) return fail(SADI_E_INVALID, "unknown g kind");
   if ((int)prec < 0 || (int)prec > 2) return fail(SADI_E_INVALID, "unknown precision");
   if (!std::isfinite(g_param)) return fail(SADI_E_INVALID, "g_param must be finite");
-  if (prec != SADI_FP64) return fail(SADI_E_UNSUPPORTED, "only float64 line solves are built");
   c->g = g;
   c->g_param = g_param;
   c->prec = prec;
@@ -410,7 +497,10 @@ sadi_status sadi_toeplitz_solve(sadi_ctx* c, double* lines, int nlines, int ld) 
   if (nlines == 0) return SADI_OK;
   if (!lines) return fail(SADI_E_INVALID, "NULL array");
   if (ld < c->n) return fail(SADI_E_INVALID, "ld must be >= N");
-  dispatch_m<RowsGS>(c->m, c, lines, ld, nlines);
+  if (c->prec == SADI_FP64)
+    dispatch_m<RowsGS>(c->m, c, lines, ld, nlines);
+  else
+    dispatch_m<RowsGSMixed>(c->m, c, lines, ld, nlines);
   return check_launch();
 }
 

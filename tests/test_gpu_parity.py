@@ -227,3 +227,57 @@ def test_full_size_step_parity(alpha):
         g2 = from_dev(u0)
     assert rel(g2, U2) < 1e-12
     assert rel(g2 - 2 * U1 + phi1, U2 - 2 * U1 + phi1) < 1e-10
+
+
+# ------------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("n,alpha", [(63, 1.5), (1023, 1.8), (4095, 1.5)])
+def test_toeplitz_solve_mixed_precision(n, alpha):
+    """FP32 Gohberg-Semencul solves: ~1e-7 alone, ~1e-13 after one FP64 residual correction."""
+    _say(f"toeplitz_solve mixed n={n} alpha={alpha}")
+    tau = 1e-3
+    P = oracle_problem(alpha, n, tau)
+    V = W.random_lines(29, n, seed=n + 1)
+    ref = P.line_solve(V)
+    errs = {}
+    for prec in ("fp32", "fp32_refine"):
+        with solver(alpha, n, tau, precision=prec) as s:
+            buf = torch.from_numpy(V).to(_dev())
+            s.toeplitz_solve(buf)
+            errs[prec] = rel(buf.cpu().numpy(), ref)
+    _say(f"  errors {errs}")
+    assert errs["fp32"] < 1e-5
+    assert errs["fp32_refine"] < 1e-12
+
+
+@pytest.mark.parametrize("n,alpha", [(63, 1.5), (1023, 1.2)])
+def test_step_mixed_precision(n, alpha):
+    _say(f"steps mixed n={n}")
+    tau = 1e-3
+    P = oracle_problem(alpha, n, tau)
+    U0 = W.asymmetric_field(n, seed=1)
+    Phi2 = 0.7 * W.asymmetric_field(n, seed=2)
+    U1 = P.first_step(U0, Phi2)
+    U2 = P.step(U0, U1)
+    for prec, tol_u, tol_hat in (("fp32_refine", 1e-12, 1e-10), ("fp32", 1e-6, 1e-5)):
+        with solver(alpha, n, tau, precision=prec) as s:
+            g1 = from_dev(s.first_step(to_dev(U0), to_dev(Phi2)))
+            up = to_dev(U0)
+            s.step(up, to_dev(U1))
+            g2 = from_dev(up)
+        assert rel(g1, U1) < tol_u, prec
+        assert rel(g2, U2) < tol_u, prec
+        assert rel(g2 - 2 * U1 + U0, U2 - 2 * U1 + U0) < tol_hat, prec
+
+
+def test_config1_run_mixed_refined():
+    wl = W.CONFIG1
+    _say("config1 run fp32_refine")
+    P = oracle_problem(wl.alpha, wl.n, wl.tau)
+    phi1, phi2 = wl.phi1(), wl.phi2()
+    ref = P.run(phi1, phi2, wl.steps)[1]
+    with solver(wl.alpha, wl.n, wl.tau, precision="fp32_refine") as s:
+        u0 = to_dev(phi1)
+        u1 = s.first_step(u0, to_dev(phi2))
+        s.run(u0, u1, wl.steps - 1)
+        got = from_dev(u1)
+    assert rel(got, ref) < 1e-10
