@@ -30,16 +30,19 @@ METRIC = "S-ADI grid-point-steps/s at N=4095 (FP64 vs FP32+refine), % HBM roofli
 
 
 def algorithmic_bytes(n: int) -> dict:
-    """Compulsory HBM bytes per launch of each kernel (float64 state, complex128 half
-    spectrum of N rows x (M+1) columns, (M+1)^2 BCCB eigenvalues)."""
+    """Compulsory HBM bytes per launch of each kernel in a run of steps (float64 state,
+    complex128 half spectrum of N rows x (M+1) columns, (M+1)^2 BCCB eigenvalues).  The
+    y-sweep leaves the increment in its workspace and the next row transform applies the
+    leapfrog update while it reads the state."""
     m = n + 1
     pts = n * n
     spec = n * (m + 1) * 16
     return {
-        "rows_fwd": pts * 8 + spec,                          # read u, write spectrum
+        # read u^n, u^{n-1} and the previous increment, write u^{n+1}, write the spectrum
+        "rows_fwd": 4 * pts * 8 + spec,
         "cols_conv": 2 * spec + (m + 1) * (m + 1) * 8,      # read+write spectrum, eigenvalues
         "rows_rhs_gs": spec + pts * 8 + pts * 8,            # read spectrum, u; write X
-        "cols_gs": 4 * pts * 8,                             # read X, u^n, u^{n-1}; write u^{n+1}
+        "cols_gs": 2 * pts * 8,                             # read X, write the increment into X
     }
 
 
@@ -89,7 +92,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 / FP32+refine runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of 1 GiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(4):
+            torch.mul(a, 1.0, out=b)      # plain elementwise kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "copies": 4}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -69,6 +69,25 @@ __device__ __forceinline__ void store_line(const V* d, double* __restrict__ v, i
     if (m < E - 1 || t < T - 1) (v + T * m * st)[t * st] = d[m].x;
 }
 
+// Same pairs for a strided line (a grid column): each element is loaded once, the reversed
+// copy comes through LDS.
+template <int M, int E, int T, class L_t>
+__device__ __forceinline__ void load_column_pair(const L_t& L, V* d, const double* __restrict__ v, int st,
+                                                 void* lds) {
+  const int t = L.t;
+  double a[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) a[m] = (m == E - 1) ? (v + T * m * st)[min(t, T - 2) * st] : (v + T * m * st)[t * st];
+  if (t == T - 1) a[E - 1] = 0.0;
+  double* buf = reinterpret_cast<double*>(lds);
+#pragma unroll
+  for (int m = 0; m < E; ++m) L.put_real(buf, t + T * m, a[m]);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = V{a[m], L.get_real(buf, (T - 1 - t) + T * (E - 1 - m))};
+  __syncthreads();
+}
+
 // ----------------------------------------------------------------------------------
 // Gohberg-Semencul solve on a line in canonical layout.  On entry slot m holds
 // v1[k] = v[k] + i v[M-1-k], k = t + T m (v the bordered right-hand side, v[M-1] = 0).
@@ -230,28 +249,44 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
 }
 
 // ----------------------------------------------------------------------------------
-// rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M
-template <int M>
+// rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M.
+// LF = 1 first completes the previous step's update: u = 2 u + (-uprev) + hat, with
+// u = ucur, hat = the increment left in X by the y-sweep; the result overwrites uprev.
+template <int M, int LF>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
-rows_fwd_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int n,
-                FFTTables<double> tab, const V* __restrict__ root2M) {
+rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
+                int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
   using L_t = typename RowCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
   __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
   const L_t L(threadIdx.x);
   const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
   const bool live = y < n;
-  const double* row = u + (size_t)(live ? y : 0) * ldu;
+  const int yy = live ? y : 0;
+  const double* row = u + (size_t)yy * ldu;
+  double* prow = LF ? uprev + (size_t)yy * ldu : nullptr;
+  const double* hrow = LF ? hat + (size_t)yy * ldx : nullptr;
+  const int t = L.t;
   V d[E];
   // z[m] = x[2m] + i x[2m+1], x[n] = 0 for n >= N = M - 1: slots c >= E/2 are zero and
   // only x[M-1] (odd part of the last nonzero z) falls outside the row
 #pragma unroll
   for (int c = 0; c < E; ++c) {
     if (c < E / 2) {
-      const int m = L.t + T * c;
-      d[c].x = row[2 * m];
-      const double odd = row[min(2 * m + 1, M - 2)];
-      d[c].y = (c == E / 2 - 1 && L.t == T - 1) ? 0.0 : odd;
+      const bool edge = (c == E / 2 - 1 && t == T - 1);
+      const int ie = 2 * t, io = edge ? 2 * T - 2 : 2 * t + 1;   // offsets from 2 T c
+      double xe = (row + 2 * T * c)[ie];
+      double xo = (row + 2 * T * c)[io];
+      if constexpr (LF == 1) {
+        xe = 2.0 * xe - (prow + 2 * T * c)[ie] + (hrow + 2 * T * c)[ie];
+        xo = 2.0 * xo - (prow + 2 * T * c)[io] + (hrow + 2 * T * c)[io];
+        if (live) {
+          (prow + 2 * T * c)[ie] = xe;
+          if (!edge) (prow + 2 * T * c)[io] = xo;
+        }
+      }
+      d[c].x = xe;
+      d[c].y = edge ? 0.0 : xo;
     } else {
       d[c] = V{0.0, 0.0};
     }
@@ -534,7 +569,7 @@ rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<
 // MODE 0: uout = 2 ucur - uprev + Uhat (uout may alias uprev); MODE 1: uout = ucur + Uhat.
 template <int M, int MODE>
 __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
-cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const double* uprev,
+cols_gs_kernel(double* X, int ldx, const double* ucur, const double* uprev,
                double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
   using Cfg = ColGSCfg<M>;
   using L_t = typename Cfg::Line;
@@ -546,13 +581,21 @@ cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const 
   const int col = grp * Cfg::LPW + L.line;
   const bool live = col < n;
   const int cc = live ? col : 0;
+  const int t = L.t;
   V d[E];
-  load_line_pair<M, E, T>(d, X + cc, ldx, L.t);
+  load_column_pair<M, E, T>(L, d, X + cc, ldx, smem);
   gs_solve(L, d, smem, tab, gs);
-  if (live) {
+  if (!live) return;
+  const int o = t * ldu + col;
+  if constexpr (MODE == 2) {
+    // the increment stays in X (the next row pass applies the update)
+    const int ox = t * ldx + col;
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      if (m < E - 1 || t < T - 1) (X + T * m * ldx)[ox] = d[m].x;
+  } else {
     // k = t + T m < N except m = E-1, t = T-1 (clamped load, no store)
-    const int o = L.t * ldu + col;
-    const int oe = min(L.t, T - 2) * ldu + col;
+    const int oe = min(t, T - 2) * ldu + col;
     double uc[E], up[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -561,7 +604,7 @@ cols_gs_kernel(const double* __restrict__ X, int ldx, const double* ucur, const 
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if (m < E - 1 || L.t < T - 1) {
+      if (m < E - 1 || t < T - 1) {
         if constexpr (MODE == 0) (uout + T * m * ldu)[o] = 2.0 * uc[m] - up[m] + d[m].x;
         else (uout + T * m * ldu)[o] = uc[m] + d[m].x;
       }
@@ -624,10 +667,31 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
 // ----------------------------------------------------------------------------------
 // host-side launchers
 template <int M>
-void launch_rows_fwd(const double* u, int ldu, V* S, int lds_, int n, const FFTTables<double>& tab,
-                     const V* root2M, hipStream_t st) {
+void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, V* S, int lds_, int n,
+                     const FFTTables<double>& tab, const V* root2M, hipStream_t st) {
   const int grid = (n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
-  hipLaunchKernelGGL(rows_fwd_kernel<M>, dim3(grid), dim3(RowCfg<M>::NT), 0, st, u, ldu, S, lds_, n, tab, root2M);
+  if (hat == nullptr)
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 0>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu, S,
+                       lds_, n, tab, root2M);
+  else
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 1>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu, S,
+                       lds_, n, tab, root2M);
+}
+
+// out = 2 ucur - uprev + hat (mode 0, out may alias uprev) or out = ucur + hat (mode 1)
+__global__ void __launch_bounds__(256)
+leapfrog_kernel(int mode, const double* ucur, const double* uprev, const double* __restrict__ hat, int ldx,
+                double* out, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (i >= n) return;
+  const size_t o = (size_t)j * n + i;
+  const double h = hat[(size_t)j * ldx + i];
+  out[o] = mode == 0 ? 2.0 * ucur[o] - uprev[o] + h : ucur[o] + h;
+}
+
+void launch_leapfrog(int mode, const double* ucur, const double* uprev, const double* hat, int ldx, double* out,
+                     int n, hipStream_t st) {
+  hipLaunchKernelGGL(leapfrog_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, mode, ucur, uprev, hat, ldx, out, n);
 }
 
 template <int M>
@@ -668,11 +732,15 @@ void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, cons
                     int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st) {
   const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
   const int grid = ((ngroups + 7) / 8) * 8;
+  double* Xw = const_cast<double*>(X);
   if (mode == 0)
-    hipLaunchKernelGGL((cols_gs_kernel<M, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, uprev, uout,
+    hipLaunchKernelGGL((cols_gs_kernel<M, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev, uout,
+                       ldu, n, tab, gs, ngroups);
+  else if (mode == 1)
+    hipLaunchKernelGGL((cols_gs_kernel<M, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev, uout,
                        ldu, n, tab, gs, ngroups);
   else
-    hipLaunchKernelGGL((cols_gs_kernel<M, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, uprev, uout,
+    hipLaunchKernelGGL((cols_gs_kernel<M, 2>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev, uout,
                        ldu, n, tab, gs, ngroups);
 }
 
@@ -711,8 +779,8 @@ void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur
 }
 
 #define SADI_INSTANTIATE(M)                                                                                      \
-  template void launch_rows_fwd<M>(const double*, int, V*, int, int, const FFTTables<double>&, const V*,         \
-                                   hipStream_t);                                                                 \
+  template void launch_rows_fwd<M>(const double*, double*, const double*, int, int, V*, int, int,              \
+                                   const FFTTables<double>&, const V*, hipStream_t);                             \
   template void launch_cols_conv<M>(V*, int, int, const double*, int, const FFTTables<double>&, const V*,        \
                                     hipStream_t);                                                                \
   template void launch_rows_rhs_gs<M>(int, const V*, int, const double*, int, const double*, double*, int, int,   \

@@ -158,8 +158,9 @@ sadi::GSTables64 gs_tables(const sadi_ctx* c) {
 }
 
 template <int M> struct RowsFwd {
-  static void run(const sadi_ctx* c, const double* u) {
-    sadi::launch_rows_fwd<M>(u, c->n, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
+  static void run(const sadi_ctx* c, const double* u, double* lf_prev) {
+    sadi::launch_rows_fwd<M>(u, lf_prev, lf_prev ? c->X : nullptr, c->ldX, c->n, c->S, c->ldS, c->n, tables(c),
+                             c->root2M, c->stream);
   }
 };
 template <int M> struct ColsConv {
@@ -231,15 +232,20 @@ sadi::StepScalars scalars(const sadi_ctx* c, bool first) {
 }
 
 // one step of the delta form on the device; mode 0: uout = 2 ucur - uprev + Uhat,
-// mode 1 (start-up): uout = ucur + Uhat with phi2
+// mode 1 (start-up): uout = ucur + Uhat with phi2.
+// Deferred update (FP64 runs): cols_mode 2 leaves Uhat in X instead of forming uout, and a
+// non-null lf_prev makes the row transform first finish the previous step's update,
+// lf_prev <- 2 ucur - lf_prev + X; the step then advances the state now held in lf_prev.
 sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double* uprev, const double* phi2,
-                         double* uout) {
+                         double* uout, int cols_mode = -1, double* lf_prev = nullptr) {
   auto mark = [&](int k) {
     hipEvent_t e = c->mark(k);
     if (e) (void)hipEventRecord(e, c->stream);
   };
+  if (cols_mode < 0) cols_mode = mode;
   mark(0);
-  dispatch_m<RowsFwd>(c->m, c, ucur);
+  dispatch_m<RowsFwd>(c->m, c, ucur, lf_prev);
+  if (lf_prev) ucur = lf_prev;
   mark(1);
   dispatch_m<ColsConv>(c->m, c);
   mark(2);
@@ -250,7 +256,7 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
     dispatch_m<RowsRhsMixed>(c->m, c, mode, ucur, phi2, sc);
   mark(3);
   if (c->prec == SADI_FP64)
-    dispatch_m<ColsGS>(c->m, c, mode, ucur, uprev, uout);
+    dispatch_m<ColsGS>(c->m, c, cols_mode, ucur, uprev, uout);
   else
     dispatch_m<ColsGSMixed>(c->m, c, mode, ucur, uprev, uout);
   mark(4);
@@ -476,10 +482,24 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
   if (nsteps < 0) return fail(SADI_E_INVALID, "nsteps must be >= 0");
   double* a = u_prev;
   double* b = u_cur;
-  for (int s = 0; s < nsteps; ++s) {
-    sadi_status st = enqueue_step(c, 0, b, a, nullptr, a);
+  if (c->prec == SADI_FP64 && nsteps > 0) {
+    // the leapfrog update of step s rides on the row transform of step s + 1
+    for (int s = 0; s < nsteps; ++s) {
+      sadi_status st = s == 0 ? enqueue_step(c, 0, b, a, nullptr, a, 2)
+                              : enqueue_step(c, 0, b, a, nullptr, a, 2, a);
+      if (st != SADI_OK) return st;
+      if (s > 0) std::swap(a, b);
+    }
+    sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
+    sadi_status st = check_launch();
     if (st != SADI_OK) return st;
     std::swap(a, b);
+  } else {
+    for (int s = 0; s < nsteps; ++s) {
+      sadi_status st = enqueue_step(c, 0, b, a, nullptr, a);
+      if (st != SADI_OK) return st;
+      std::swap(a, b);
+    }
   }
   if (nsteps % 2 == 1) {
     // newest is in u_prev's buffer: exchange the two arrays through the X workspace
@@ -508,7 +528,7 @@ sadi_status sadi_apply_lh(sadi_ctx* c, const double* u, double* out) {
   if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
   if (!u || !out) return fail(SADI_E_INVALID, "NULL array");
   if (u == out) return fail(SADI_E_INVALID, "u and out must differ");
-  dispatch_m<RowsFwd>(c->m, c, u);
+  dispatch_m<RowsFwd>(c->m, c, u, nullptr);
   dispatch_m<ColsConv>(c->m, c);
   sadi::StepScalars sc{};
   sc.sigma = c->h_alpha;

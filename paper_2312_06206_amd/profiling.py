@@ -58,3 +58,53 @@ def find_csv(directory: str, suffix: str = "counter_collection.csv") -> str:
     if not hits:
         raise FileNotFoundError(f"no *{suffix} under {directory}")
     return sorted(hits)[-1]
+
+
+KERNEL_KEYS = {"rows_fwd": "rows_fwd_kernel<", "cols_conv": "cols_conv_kernel<",
+               "rows_rhs_gs": "rows_rhs_gs_kernel<", "cols_gs": "cols_gs_kernel<"}
+
+
+def _mean_by_kernel(path: str, counter: str, m: int) -> dict:
+    """Mean counter value per dispatch of the n >= 1 step kernels of length m."""
+    import csv
+    acc: dict = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row.get("Kernel_Name", "")
+            for key, pat in KERNEL_KEYS.items():
+                if f"{pat}{m}" in name:
+                    if key in ("rows_rhs_gs", "cols_gs") and f"{pat}{m}, 0>" not in name:
+                        continue
+                    acc.setdefault(key, []).append(float(row["Counter_Value"]))
+            if "elementwise" in name and "Mul" in name:
+                acc.setdefault("_copy", []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def write_traffic_summary(fetch_dir: str, write_dir: str, calib_fetch_dir: str, calib_write_dir: str,
+                          n: int, out_json: str, command: str) -> dict:
+    """Combine FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) of the benchmark and of the
+    copy calibration into bytes per launch for each step kernel."""
+    m = n + 1
+    fetch = _mean_by_kernel(find_csv(fetch_dir), "FETCH_SIZE", m)
+    write = _mean_by_kernel(find_csv(write_dir), "WRITE_SIZE", m)
+    cf = _mean_by_kernel(find_csv(calib_fetch_dir), "FETCH_SIZE", m)["_copy"]
+    cw = _mean_by_kernel(find_csv(calib_write_dir), "WRITE_SIZE", m)["_copy"]
+    copy_bytes = float(1 << 30)
+    f_fetch = cf * 1024.0 / copy_bytes        # counter bytes per true byte, reads
+    f_write = cw * 1024.0 / copy_bytes
+    rec = {"workload": f"N{n}", "command": command, "source_hash": source_hash(),
+           "calibration": {"copy_bytes": copy_bytes, "fetch_kib_per_copy": cf, "write_kib_per_copy": cw,
+                           "fetch_factor": f_fetch, "write_factor": f_write},
+           "kernels": {}}
+    for k in KERNEL_KEYS:
+        if k in fetch and k in write:
+            rb = fetch[k] * 1024.0 / f_fetch
+            wb = write[k] * 1024.0 / f_write
+            rec["kernels"][k] = {"fetch_kib": fetch[k], "write_kib": write[k], "read_bytes": rb,
+                                 "write_bytes": wb, "bytes_per_launch": rb + wb}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
