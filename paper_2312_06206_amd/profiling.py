@@ -60,8 +60,17 @@ def find_csv(directory: str, suffix: str = "counter_collection.csv") -> str:
     return sorted(hits)[-1]
 
 
-KERNEL_KEYS = {"rows_fwd": "rows_fwd_kernel<", "cols_conv": "cols_conv_kernel<",
-               "rows_rhs_gs": "rows_rhs_gs_kernel<", "cols_gs": "cols_gs_kernel<"}
+# the kernels of a step n >= 1 inside a multi-step run, by name prefix and template tail
+KERNEL_KEYS = {"rows_fwd": ("rows_fwd_kernel<", ", 1>"), "cols_conv": ("cols_conv_kernel<", ">"),
+               "rows_rhs_gs": ("rows_rhs_gs_kernel<", ", 0>"), "cols_gs": ("cols_gs_kernel<", ", 2>")}
+
+
+def kernel_key(name: str, m: int):
+    """Step-kernel key of a demangled kernel name for line length m, or None."""
+    for key, (head, tail) in KERNEL_KEYS.items():
+        if f"{head}{m}{tail}" in name:
+            return key
+    return None
 
 
 def _mean_by_kernel(path: str, counter: str, m: int) -> dict:
@@ -73,14 +82,38 @@ def _mean_by_kernel(path: str, counter: str, m: int) -> dict:
             if row.get("Counter_Name") != counter:
                 continue
             name = row.get("Kernel_Name", "")
-            for key, pat in KERNEL_KEYS.items():
-                if f"{pat}{m}" in name:
-                    if key in ("rows_rhs_gs", "cols_gs") and f"{pat}{m}, 0>" not in name:
-                        continue
-                    acc.setdefault(key, []).append(float(row["Counter_Value"]))
+            key = kernel_key(name, m)
+            if key:
+                acc.setdefault(key, []).append(float(row["Counter_Value"]))
             if "elementwise" in name and "Mul" in name:
                 acc.setdefault("_copy", []).append(float(row["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def write_kernel_stats_summary(stats_csv: str, n: int, out_md: str, command: str) -> dict:
+    """Short markdown table of a `rocprofv3 --kernel-trace --stats` kernel_stats.csv: calls,
+    average and total duration of every kernel, step kernels labelled."""
+    import csv
+    m = n + 1
+    rows = []
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["TotalDurationNs"]),
+                         float(r.get("Percentage", 0.0))))
+    rows.sort(key=lambda r: -r[3])
+    steps = {}
+    lines = [f"# Kernel trace, S-ADI FP64, N={n}", "", "Command (from the repository root):", "",
+             "```", command, "```", "",
+             "| kernel | step role | calls | avg us | total ms | % |", "|---|---|---|---|---|---|"]
+    for name, calls, avg, tot, pct in rows:
+        short = name.split("(")[0].replace("void ", "").replace("sadi::", "")
+        key = kernel_key(name, m) or ""
+        if key:
+            steps[key] = {"calls": calls, "avg_us": avg / 1e3}
+        lines.append(f"| `{short[:70]}` | {key} | {calls} | {avg / 1e3:.1f} | {tot / 1e6:.3f} | {pct:.1f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return steps
 
 
 def write_traffic_summary(fetch_dir: str, write_dir: str, calib_fetch_dir: str, calib_write_dir: str,

@@ -56,7 +56,8 @@ def solver(alpha, n, tau, kappa=1.0, g="neg_sin", domain=(-1.0, 1.0), g_param=0.
 
 
 # ------------------------------------------------------------------ line solves
-@pytest.mark.parametrize("n,alpha", [(15, 1.5), (63, 1.2), (255, 1.8), (1023, 1.5), (4095, 1.5), (4095, 1.8)])
+@pytest.mark.parametrize("n,alpha", [(15, 1.5), (31, 1.3), (63, 1.2), (127, 1.6), (255, 1.8), (511, 1.4),
+                                     (1023, 1.5), (2047, 1.5), (4095, 1.5), (4095, 1.8)])
 def test_toeplitz_solve(n, alpha):
     _say(f"toeplitz_solve n={n} alpha={alpha}")
     tau = 1e-3 if n > 63 else 1 / 64
@@ -126,9 +127,11 @@ def test_config1_run():
     assert rel(got_prev, ref_prev) < 1e-10
 
 
-@pytest.mark.parametrize("nsteps", [6, 7])
-def test_run_even_and_odd_counts(nsteps):
-    n, alpha, tau = 127, 1.6, 2e-3
+@pytest.mark.parametrize("n,nsteps", [(127, 0), (127, 1), (127, 2), (127, 6), (127, 7), (31, 3), (1023, 4)])
+def test_run_even_and_odd_counts(n, nsteps):
+    """Runs of zero, one and several steps (the update of each step is deferred into the
+    next step's row transform; an odd count exchanges the two arrays at the end)."""
+    alpha, tau = 1.6, 2e-3
     _say(f"run parity n={n} steps={nsteps}")
     P = oracle_problem(alpha, n, tau)
     U0 = W.asymmetric_field(n, seed=5)
@@ -227,6 +230,26 @@ def test_full_size_step_parity(alpha):
         g2 = from_dev(u0)
     assert rel(g2, U2) < 1e-12
     assert rel(g2 - 2 * U1 + phi1, U2 - 2 * U1 + phi1) < 1e-10
+
+
+def test_full_size_run_parity():
+    """N = 4095: three steps through sadi_run (the benchmark's launch sequence) against the
+    oracle stepping from the same two states."""
+    wl = W.config2(4095, 1.5, seed=0)
+    _say("full size run parity")
+    P = oracle_problem(wl.alpha, wl.n, wl.tau)
+    U0 = W.asymmetric_field(wl.n, seed=23) + wl.phi1()
+    U1 = U0 + 1e-3 * W.asymmetric_field(wl.n, seed=24)
+    prev, cur = U0, U1
+    for _ in range(3):
+        prev, cur = cur, P.step(prev, cur)
+    with solver(wl.alpha, wl.n, wl.tau) as s:
+        u0, u1 = to_dev(U0), to_dev(U1)
+        s.run(u0, u1, 3)
+        got_cur, got_prev = from_dev(u1), from_dev(u0)
+    assert rel(got_cur, cur) < 1e-12
+    assert rel(got_prev, prev) < 1e-12
+    assert rel(got_cur - 2 * got_prev, cur - 2 * prev) < 1e-11
 
 
 # ------------------------------------------------------------------ mixed precision
