@@ -22,6 +22,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 namespace sadi {
 
 template <typename R> struct vec2;
@@ -77,6 +79,42 @@ __device__ __forceinline__ V tw16(V a) {
   else if constexpr (j == 11) return mul_cs<DIR>(a, (R)-SADI_S8_1, (R)-SADI_C8_1);
   else if constexpr (j == 13) return mul_cs<DIR>(a, (R)SADI_S8_1, (R)-SADI_C8_1);
   else return mul_cs<DIR>(a, (R)SADI_C8_1, (R)-SADI_S8_1);  // 15
+}
+
+// cos(pi j/16), j = 0..8
+#define SADI_C16_1 0.98078528040323044912618223613423903697L
+#define SADI_C16_3 0.83146961230254523707878837761790575674L
+#define SADI_C16_5 0.55557023301960222474283081394853287437L
+#define SADI_C16_7 0.19509032201612826784828486847702224093L
+
+template <int J> struct Cos16;   // cos(pi J / 16) for J in [0, 8]
+template <> struct Cos16<0> { static constexpr long double v = 1.0L; };
+template <> struct Cos16<1> { static constexpr long double v = SADI_C16_1; };
+template <> struct Cos16<2> { static constexpr long double v = SADI_C8_1; };
+template <> struct Cos16<3> { static constexpr long double v = SADI_C16_3; };
+template <> struct Cos16<4> { static constexpr long double v = SADI_R2; };
+template <> struct Cos16<5> { static constexpr long double v = SADI_C16_5; };
+template <> struct Cos16<6> { static constexpr long double v = SADI_S8_1; };
+template <> struct Cos16<7> { static constexpr long double v = SADI_C16_7; };
+template <> struct Cos16<8> { static constexpr long double v = 0.0L; };
+
+// multiply by e^{SH i pi j / 16} for a compile-time j in [0, 16), SH = +-1
+template <int SH, int J, typename V>
+__device__ __forceinline__ V shift16(V a) {
+  using R = decltype(a.x);
+  if constexpr (J == 0) return a;
+  else if constexpr (J == 8) return mul_i<SH>(a);
+  else {
+    constexpr long double c = J < 8 ? Cos16<(J < 8 ? J : 0)>::v : -Cos16<(J > 8 ? 16 - J : 0)>::v;
+    constexpr long double sn = J < 8 ? Cos16<(J < 8 ? 8 - J : 0)>::v : Cos16<(J > 8 ? J - 8 : 0)>::v;
+    return mul_cs<SH>(a, (R)c, (R)sn);
+  }
+}
+
+// d[c] *= e^{SH i pi c STEP / 16} for every slot c
+template <int SH, int STEP, typename V, int... C>
+__device__ __forceinline__ void shift_slots(V* d, std::integer_sequence<int, C...>) {
+  ((d[C] = shift16<SH, C * STEP>(d[C])), ...);
 }
 
 // ---- in-register DFTs, natural order in and out ------------------------------
@@ -175,6 +213,34 @@ template <int N, typename V> __device__ __forceinline__ void twiddle_powers(V* a
   }
 }
 
+// a[k] *= s w^k, k = 0..N-1 (the same product structure with every power scaled by s)
+template <int N, typename V> __device__ __forceinline__ void twiddle_powers_s(V* a, V w, V s) {
+  a[0] = cmul(a[0], s);
+  if constexpr (N == 1) return;
+  a[1] = cmul(a[1], cmul(s, w));
+  if constexpr (N >= 4) {
+    const V w2 = cmul(w, w);
+    V r = cmul(s, w2);
+    a[2] = cmul(a[2], r);
+    a[3] = cmul(a[3], cmul(r, w));
+    if constexpr (N >= 8) {
+      const V w4 = cmul(w2, w2);
+      V g = cmul(s, w4);
+#pragma unroll
+      for (int q = 1; q < N / 4; ++q) {
+        if (q > 1) g = cmul(g, w4);
+        a[4 * q] = cmul(a[4 * q], g);
+        r = cmul(g, w);
+        a[4 * q + 1] = cmul(a[4 * q + 1], r);
+        r = cmul(g, w2);
+        a[4 * q + 2] = cmul(a[4 * q + 2], r);
+        r = cmul(r, w);
+        a[4 * q + 3] = cmul(a[4 * q + 3], r);
+      }
+    }
+  }
+}
+
 // e^{DIR 2 pi i j / N} from a table of forward roots e^{-2 pi i j / N}
 template <int DIR, typename V> __device__ __forceinline__ V root(const V* tab, int j) {
   V w = tab[j];
@@ -200,6 +266,7 @@ template <> struct Shape<4096> { static constexpr int E = 16, P2 = 16; };
 template <typename R> struct FFTTables {
   const V2<R>* rootM;
   const V2<R>* rootS;
+  const V2<R>* root2M;   // e^{-i pi j/M}, j < M (half-bin shifted transforms)
 };
 
 // LPW lines per workgroup.  LDS exchange region: SPLIT==1 -> V2<R> per element,
@@ -237,11 +304,32 @@ struct Line {
   }
 
   // write value v (all SPLIT rounds are handled by the caller through exchange())
-  template <int DIR>
+  // SH = +-1: transform of x[n] e^{SH i pi n/M} instead of x[n] (a half-bin shift, e.g. the
+  // skew-circulant diagonalisation).  With n = t + T c the factor splits into e^{SH i pi c/E}
+  // per slot (constants, before the first DFT) and e^{SH i pi t/M} per thread, which starts
+  // the running product of the first twiddle.
+  template <int DIR, int SH = 0>
   __device__ __forceinline__ void transform(V* d, void* lds, const FFTTables<R>& tab) const {
     // ---- stage 1: DFT_E over c, twiddle W_M^{t k1}
+    if constexpr (SH != 0) shift_slots<SH, 16 / E>(d, std::make_integer_sequence<int, E>{});
     dft<E, DIR>(d);
-    twiddle_powers<E>(d, root<DIR>(tab.rootM, t));
+    if constexpr (SH == 0) twiddle_powers<E>(d, root<DIR>(tab.rootM, t));
+    else twiddle_powers_s<E>(d, root<DIR>(tab.rootM, t), root<SH>(tab.root2M, t));
+    stages23<DIR>(d, lds, tab);
+  }
+
+  // Same with a per-thread factor s on the first twiddle (the caller has applied any
+  // per-slot factor): a half-bin shift that only some lines of a workgroup take.
+  template <int DIR>
+  __device__ __forceinline__ void transform_scaled(V* d, void* lds, const FFTTables<R>& tab, V s) const {
+    dft<E, DIR>(d);
+    twiddle_powers_s<E>(d, root<DIR>(tab.rootM, t), s);
+    stages23<DIR>(d, lds, tab);
+  }
+
+  // exchanges, stage 2 and stage 3 (natural-order output in canonical layout)
+  template <int DIR>
+  __device__ __forceinline__ void stages23(V* d, void* lds, const FFTTables<R>& tab) const {
     if constexpr (P2 == 1) {
       // single exchange: writer t = a holds k1; reader t3 = k1 gathers a
       exchange(d, lds, [&](int k1) { return k1 + (T + PAD) * t; },

@@ -136,14 +136,12 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V2<typename LineT::Real
   using R = typename LineT::Real;
   constexpr int M = LineT::M, E = LineT::E, T = LineT::T;
   const int t = L.t;
-  // v2 = Q^H ifft(lam_s o fft(Q v1))
-  pointwise<E, T, false>(d, gs.q, t);
-  L.template transform<-1>(d, lds, tab);
+  // v2 = Q^H ifft(lam_s o fft(Q v1)); Q = diag(e^{-i pi k/M}) rides on the transform
+  L.template transform<-1, -1>(d, lds, tab);
   pointwise<E, T, false>(d, gs.lam_s, t);
   L.template transform<+1>(d, lds, tab);
-  pointwise<E, T, true>(d, gs.q, t);
-  // v3 = ifft(lam_c o fft(v2))
-  L.template transform<-1>(d, lds, tab);
+  // v3 = ifft(lam_c o fft(v2)), the Q^H of v2 again folded into the transform
+  L.template transform<-1, +1>(d, lds, tab);
   pointwise<E, T, false>(d, gs.lam_c, t);
   L.template transform<+1>(d, lds, tab);
   // w = Re(v3) + J Im(v3); bordering correction w[:N] - f * w[N]
@@ -334,6 +332,22 @@ rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const 
   }
 }
 
+// f(integral_constant<int, C>) for every slot C, in order
+template <typename F, int... C>
+__device__ __forceinline__ void for_slots(F f, std::integer_sequence<int, C...>) {
+  (f(std::integral_constant<int, C>{}), ...);
+}
+
+// d[c] *= e^{-i pi c/E} where `odd` (per lane), else unchanged
+template <int E, typename VV, int... C>
+__device__ __forceinline__ void shift_odd_slots(VV* d, bool odd, std::integer_sequence<int, C...>) {
+  ((d[C] = odd ? shift16<-1, C * (16 / E)>(d[C]) : d[C]), ...);
+}
+template <typename VV, int... C>
+__device__ __forceinline__ void shift_odd_slots(VV* d, bool odd, std::integer_sequence<int, C...> seq) {
+  shift_odd_slots<(int)sizeof...(C)>(d, odd, seq);
+}
+
 // ----------------------------------------------------------------------------------
 // cols_conv: for every x-frequency column kx (0..M): c[y] = S[y][kx] (y < N, zero to P),
 // out = IFFT_P(Lambda[kx] o FFT_P(c)), first N rows.  The length-P transform is split
@@ -364,16 +378,11 @@ cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ 
   for (int m = 0; m < E; ++m)
     d[m] = (m == E - 1) ? (S + T * m * lds_)[min(t, T - 2) * lds_ + colc] : (S + T * m * lds_)[so];
   if (t == T - 1) d[E - 1] = V{0.0, 0.0};
-#pragma unroll
-  for (int g = 0; g < E; g += 4) {
-    V w[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) w[j] = (root2M + T * (g + j))[t];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) d[g + j] = odd ? cmul(d[g + j], w[j]) : d[g + j];
-    asm volatile("" ::: "memory");
-  }
-  L.template transform<-1>(d, smem, tab);
+  // odd lines: W_P^y = e^{-i pi y/M} on the input, y = t + T m: the per-slot part
+  // e^{-i pi m/E} here, the per-thread part e^{-i pi t/M} on the first twiddle
+  shift_odd_slots(d, odd, std::make_integer_sequence<int, E>{});
+  const V s0 = root2M[t];
+  L.template transform_scaled<-1>(d, smem, tab, odd ? s0 : V{1.0, 0.0});
   // eigenvalues of the embedding, row kx: [Lam_e(0..M/2), Lam_o(0..M/2-1)] (even in ky):
   //   k < M/2 : even Lam_e[k],       odd Lam_o[k]           -> k + odd (M/2 + 1)
   //   k >= M/2: even Lam_e[M-k],     odd Lam_o[M-1-k]       -> M - k + odd (M/2)
@@ -397,17 +406,13 @@ cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ 
   V* xb = reinterpret_cast<V*>(smem);
   static_assert(Cfg::LINE_FAST, "column pairing assumes interleaved lines");
   const int xo = t * CPW + L.line / 2;
+  if (odd) {
+    // W_P^{-y}, y = t + T m: e^{i pi t/M} (conjugate of s0) times e^{i pi m/E}
 #pragma unroll
-  for (int g = 0; g < E; g += 4) {
-    V w[4];
+    for (int m = 0; m < E; ++m) d[m] = cmulc(d[m], s0);
+    shift_slots<+1, 16 / E>(d, std::make_integer_sequence<int, E>{});
 #pragma unroll
-    for (int j = 0; j < 4; ++j) w[j] = (root2M + T * (g + j))[t];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const V v = cmulc(d[g + j], w[j]);
-      if (odd) (xb + T * CPW * (g + j))[xo] = v;
-    }
-    asm volatile("" ::: "memory");
+    for (int m = 0; m < E; ++m) (xb + T * CPW * m)[xo] = d[m];
   }
   __syncthreads();
   if (!odd && live) {
@@ -436,25 +441,17 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
   // c2r pre-processing: Z[k] = FE[k] + i FO[k], FE = (X[k] + conj X[M-k])/2,
   // FO = W_P^{-k} (X[k] - conj X[M-k])/2 ; the 1/2 is folded into Lambda.
   // X[M-k] with M-k = (M - T m) - t: uniform base minus the lane index
-#pragma unroll
-  for (int g = 0; g < E; g += 4) {
-    V xk[4], xm[4], w[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = g + j;
-      xk[j] = (srow + T * m)[t];
-      xm[j] = (srow + (M - T * m))[-t];
-      w[j] = (root2M + T * m)[t];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const V c = cconj(xm[j]);
-      const V fe = cadd(xk[j], c);
-      const V fo = cmulc(csub(xk[j], c), w[j]);
-      d[g + j] = V{fe.x - fo.y, fe.y + fo.x};
-    }
-    asm volatile("" ::: "memory");
-  }
+  // W_P^{-k}, k = t + T m: e^{i pi t/M} (conjugate of root2M[t]) times e^{i pi m/E}
+  const V s0 = root2M[t];
+  for_slots([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+    const V xk = (srow + T * m)[t];
+    const V c = cconj((srow + (M - T * m))[-t]);
+    const V fe = cadd(xk, c);
+    const V fo = shift16<+1, m * (16 / E)>(cmulc(csub(xk, c), s0));
+    d[m] = V{fe.x - fo.y, fe.y + fo.x};
+    if constexpr (m % 4 == 3) asm volatile("" ::: "memory");
+  }, std::make_integer_sequence<int, E>{});
   L.template transform<+1>(d, smem, tab);
   // slot m holds z[j], j = t + T m: x[2j] = Re, x[2j+1] = Im; only j < M/2 (slots
   // m < E/2) carry x[i] with i < M, and x[M-1] (j = M/2-1, odd part) is outside the grid
@@ -472,17 +469,46 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
   } else {
     // x[2j + h], j = t + T m: uniform base 2 T m, lane offset 2 t + h; x[N] (the last odd
     // value of slot E/2-1 of lane T-1) is outside the grid and B[N] = 0
+    // first sigma x (frees the transform's registers), then the pointwise terms are added
+    // in place: each thread only touches its own LDS entries, so no barrier in between
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const bool last = (h == 1 && m == E / 2 - 1);
-        const int lane_off = last ? min(2 * t + 1, 2 * T - 2) : 2 * t + h;
-        const double uv = (urow + 2 * T * m)[lane_off];
         const double xv = h ? d[m].y : d[m].x;
-        double b = sc.sigma * xv + sc.gamma * g_of(uv, sc.gkind, sc.gparam);
+        L.put_real(buf, 2 * (t + T * m) + h, (last && t == T - 1) ? 0.0 : sc.sigma * xv);
+      }
+    }
+    bool far = false;   // some sin argument beyond the fast reduction's range
+#pragma unroll
+    for (int m = 0; m < E / 2; ++m) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool last = (h == 1 && m == E / 2 - 1);
+        if (last && t == T - 1) continue;       // B[N] = 0
+        const int lane_off = 2 * t + h;
+        const double uv = (urow + 2 * T * m)[lane_off];
+        far |= !(fabs(uv) <= kSinFastMax);
+        double b = sc.gamma * g_of(uv, sc.gkind, sc.gparam);
         if constexpr (MODE == 1) b += sc.tau * (prow + 2 * T * m)[lane_off];
-        L.put_real(buf, 2 * (t + T * m) + h, (last && t == T - 1) ? 0.0 : b);
+        const int k = 2 * (t + T * m) + h;
+        L.put_real(buf, k, L.get_real(buf, k) + b);
+      }
+      if (m % 2 == 1) asm volatile("" ::: "memory");   // bound the live sine temporaries
+    }
+    if (sc.gkind == 1 && far) {
+      // rare: replace the fast sine by the library's for the far arguments of this lane
+#pragma unroll 1
+      for (int i = 0; i < E; ++i) {
+        const int m = i >> 1, h = i & 1;
+        const bool last = (h == 1 && m == E / 2 - 1);
+        if (last && t == T - 1) continue;
+        const double uv = (urow + 2 * T * m)[2 * t + h];
+        if (!(fabs(uv) <= kSinFastMax)) {
+          const int k = 2 * (t + T * m) + h;
+          L.put_real(buf, k, L.get_real(buf, k) + sc.gamma * (sin_fp64(uv) - sin(uv)));
+        }
       }
     }
     __syncthreads();

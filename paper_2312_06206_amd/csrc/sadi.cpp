@@ -152,7 +152,7 @@ ShapeInfo shape_of(int m) {
   }
 }
 
-sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS}; }
+sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS, c->root2M}; }
 sadi::GSTables64 gs_tables(const sadi_ctx* c) {
   return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f};
 }
@@ -188,7 +188,7 @@ template <int M> struct RowsGS {
 
 sadi::MixedTables mixed_tables(const sadi_ctx* c) {
   sadi::MixedTables mx{};
-  mx.tab32 = sadi::FFTTables<float>{c->rootM32, c->rootS32};
+  mx.tab32 = sadi::FFTTables<float>{c->rootM32, c->rootS32, c->q32};
   mx.gs32 = sadi::GSTables<float>{c->q32, c->lam_s32, c->lam_c32, c->f32};
   mx.toe = sadi::ToeplitzTables64{c->sig_e, c->sig_o};
   mx.q64 = c->root2M;

@@ -110,6 +110,29 @@ def test_first_step_and_step(n, alpha, tau, g):
     assert rel(g2 - 2 * U1 + U0, U2 - 2 * U1 + U0) < 1e-11
 
 
+@pytest.mark.parametrize("kappa,far", [(1.0, False), (1e-12, True)])
+def test_sine_nonlinearity_over_many_periods(kappa, far):
+    """g = -sin u on a field spanning about +-60 (many periods of sin, both signs); with
+    far = True also values beyond the fast sine's reduction range (library fallback).  The
+    g-part of the increment, i.e. the difference of the g = -sin u and g = 0 start-up
+    steps, is compared with the oracle's.  A tiny kappa keeps the L_h part (which cancels
+    in the difference up to its rounding) small next to the g-part when |u| is huge."""
+    n, alpha, tau = 127, 1.5, 0.05
+    _say(f"sine nonlinearity kappa={kappa} far={far}")
+    U0 = 25.0 * W.asymmetric_field(n, seed=31)
+    if far:
+        U0[5, 7], U0[60, 3], U0[100, 100] = 3.0e5, -7.5e6, 1.0e5
+    Phi2 = np.zeros_like(U0)
+    out = {}
+    for g in ("neg_sin", "zero"):
+        P = oracle_problem(alpha, n, tau, kappa=kappa, g=g)
+        with solver(alpha, n, tau, kappa=kappa, g=g) as s:
+            out[g] = (from_dev(s.first_step(to_dev(U0), to_dev(Phi2))) - U0, P.first_step(U0, Phi2) - U0)
+    got = out["neg_sin"][0] - out["zero"][0]
+    ref = out["neg_sin"][1] - out["zero"][1]
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+
+
 # ------------------------------------------------------------------ whole runs
 def test_config1_run():
     """Omega=(-1,1)^2, N=63, alpha=1.5, kappa=1, g=-sin u, phi1=exp(-10 r^2), phi2=0, tau=1/64, 64 steps."""
