@@ -81,6 +81,64 @@ def cpu_baseline(wl, sample_steps: int) -> dict:
                       f"{threads} FFT workers and BLAS threads"}
 
 
+def batched_leg(seed: int, count: int, steps: int, unbatched_sample: int) -> dict:
+    """Uneven batch: `count` problems with N uniform over {127, 255, 511, 1023}, alpha ~
+    U(1.1, 1.9), kappa ~ U(0.5, 2), seeded Gaussian phi1, phi2 = 0, tau = 1e-3; autotuned
+    line-sweep path per N, `steps` steps replayed from a HIP graph.  Compared with the same
+    problems run one by one through the single-instance FP64 path."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2312_06206_amd import Batch, Solver
+
+    dev = torch.device("cuda:0")
+    ms = W.batch_members(count, seed)
+    tau = 1e-3
+    t0 = time.perf_counter()
+    b = Batch([m.n for m in ms], [m.alpha for m in ms], [m.kappa for m in ms], tau, dense_max_n=1023)
+    setup_s = time.perf_counter() - t0
+    u0 = [torch.from_numpy(np.ascontiguousarray(m.phi1().T)).to(dev) for m in ms]
+    u1 = [torch.zeros_like(t) for t in u0]
+    p2 = [torch.zeros_like(t) for t in u0]
+    b.bind(u0, u1, p2)
+    t0 = time.perf_counter()
+    groups = b.tune(steps=5)
+    tune_s = time.perf_counter() - t0
+    b.set_graph(True)
+    b.first_step()
+    b.run(4)                                   # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    finite = all(bool(torch.isfinite(t).all().item()) for t in u1)
+    pts = sum(m.n * m.n for m in ms)
+    b.close()
+
+    # the same problems one at a time (sampled steps per instance, extrapolated)
+    one_ms = 0.0
+    for m in ms:
+        s = Solver(m.alpha, m.kappa, m.n, tau)
+        a = torch.from_numpy(np.ascontiguousarray(m.phi1().T)).to(dev)
+        c = s.first_step(a, torch.zeros_like(a))
+        s.run(a, c, 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.run(a, c, unbatched_sample)
+        torch.cuda.synchronize()
+        one_ms += 1e3 * (time.perf_counter() - t1) / unbatched_sample
+        s.close()
+    batch_ms = 1e3 * dt / steps
+    return {"workload": f"{count} instances, N uniform over {{127,255,511,1023}}, alpha~U(1.1,1.9), "
+                        f"kappa~U(0.5,2), seeded Gaussian phi1, phi2=0, tau=1e-3, seed {seed}",
+            "steps": steps, "ms_per_step": batch_ms, "value": pts * steps / dt, "unit": "grid-point-steps/s",
+            "one_by_one_ms_per_step": one_ms, "speedup_vs_one_by_one": one_ms / batch_ms,
+            "groups": groups, "setup_s": setup_s, "tune_s": tune_s, "graph": True, "finite": finite,
+            "one_by_one_sample_steps": unbatched_sample}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +150,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 / FP32+refine runs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (uneven N) leg")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -202,6 +263,8 @@ def main():
         "precision_variants": variants,
     }
     s.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(args.seed, args.batch_count, args.batch_steps, 20)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)

@@ -153,6 +153,71 @@ sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out);
 sadi_status sadi_host_line_generator(double alpha, double kappa, int n, double tau, const double* domain,
                                      double* out);
 
+/* ---------------------------------------------------------------------------------
+ * Batches: many independent problems of the same scheme (same tau, domain and g = -sin u,
+ * FP64), each with its own N, alpha and kappa, advanced together.  Instances with equal N
+ * form a group; every phase of a step (the four passes of the delta form above) is one
+ * launch over all instances of a group.  The two line sweeps of a group take one of two
+ * paths:
+ *   SADI_PATH_FFT_GS  the Gohberg-Semencul line solves (Proposition 1, Algorithm 1);
+ *   SADI_PATH_DENSE   X = H^-1 B H^-1 as two batched FP64 matrix products with the explicit
+ *                     inverse (H is fixed for the whole run, section "Fast implementation
+ *                     based on GS formula"), computed once at creation by the line solve
+ *                     on the identity.
+ * sadi_batch_tune times both and keeps the faster per group.  Multi-step runs can be
+ * replayed from a captured HIP graph.  The batch works on its own HIP stream (see
+ * sadi_batch_synchronize); the caller must have finished writing the bound arrays
+ * before a call and must synchronise before reading them. */
+typedef struct sadi_batch sadi_batch;
+
+typedef enum { SADI_PATH_FFT_GS = 0, SADI_PATH_DENSE = 1 } sadi_line_path;
+
+/* count instances; n, alpha, kappa: host arrays of count entries (each validated as in
+ * sadi_setup); tau and domain (host, 2 doubles) are shared.  Groups with N <= dense_max_n
+ * also get the explicit inverse (N*N doubles per instance) for SADI_PATH_DENSE.
+ * Host-synchronous; allocates everything the batch needs.  All groups start on
+ * SADI_PATH_FFT_GS. */
+sadi_status sadi_batch_create(int count, const int* n, const double* alpha, const double* kappa, double tau,
+                              const double* domain, int dense_max_n, sadi_batch** out);
+
+/* Bind the state: host arrays of count DEVICE pointers, each an N_i*N_i float64 grid in
+ * the layout above (caller-owned).  u_prev[i] holds u^{n-1} (or phi1 before the start-up
+ * step), u_cur[i] holds u^n.  phi2 (may be NULL unless sadi_batch_first_step is used):
+ * start-up velocities.  Host-synchronous (uploads the instance descriptors). */
+sadi_status sadi_batch_bind(sadi_batch* b, double* const* u_prev, double* const* u_cur, const double* const* phi2);
+
+/* Start-up step of every instance (delta form, n = 0): u_cur <- u^1 from u_prev = phi1. */
+sadi_status sadi_batch_first_step(sadi_batch* b);
+
+/* nsteps steps n >= 1 of every instance, in place: on return u_prev, u_cur hold
+ * u^{n+nsteps-1}, u^{n+nsteps}.  Asynchronous on the batch stream; no allocation (the
+ * first call with graphs enabled captures and instantiates the graph). */
+sadi_status sadi_batch_run(sadi_batch* b, int nsteps);
+
+/* enable != 0: sadi_batch_run replays two steps at a time from a captured HIP graph. */
+sadi_status sadi_batch_set_graph(sadi_batch* b, int enable);
+
+/* Force the line-sweep path of the group with this N (SADI_E_UNSUPPORTED for
+ * SADI_PATH_DENSE above dense_max_n). */
+sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path);
+
+/* Autotuner: for every group, time `steps` steps of each available path on zero scratch
+ * state (the bound state is not touched) and keep the faster path.  Host-synchronous. */
+sadi_status sadi_batch_tune(sadi_batch* b, int steps);
+
+/* Group `index` (0 <= index < groups): its N, member count, current path and the tuned
+ * milliseconds per step of each path (-1 if not timed). */
+sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,
+                                 double* ms_dense);
+
+/* Instance and group counts, device bytes held by the batch. */
+sadi_status sadi_batch_get_info(const sadi_batch* b, int* count, int* groups, long long* bytes);
+
+/* Wait for all work queued on the batch stream. */
+sadi_status sadi_batch_synchronize(sadi_batch* b);
+
+sadi_status sadi_batch_destroy(sadi_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,7 @@ if it has not been built (`python -m paper_2312_06206_amd.build`).
 """
 from .binding import (  # noqa: F401
     LIB_PATH,
+    Batch,
     SadiError,
     Solver,
     host_laplacian_coeffs,

@@ -60,6 +60,17 @@ def load_library() -> ctypes.CDLL:
         "sadi_host_riesz_coeffs": (I, [D, I, DP]),
         "sadi_host_laplacian_coeffs": (I, [D, I, DP]),
         "sadi_host_line_generator": (I, [D, D, I, D, DP, DP]),
+        "sadi_batch_create": (I, [I, P(I), DP, DP, D, DP, I, P(VP)]),
+        "sadi_batch_bind": (I, [VP, P(VP), P(VP), P(VP)]),
+        "sadi_batch_first_step": (I, [VP]),
+        "sadi_batch_run": (I, [VP, I]),
+        "sadi_batch_set_graph": (I, [VP, I]),
+        "sadi_batch_set_path": (I, [VP, I, I]),
+        "sadi_batch_tune": (I, [VP, I]),
+        "sadi_batch_get_group": (I, [VP, I, P(I), P(I), P(I), DP, DP]),
+        "sadi_batch_get_info": (I, [VP, P(I), P(I), P(ctypes.c_longlong)]),
+        "sadi_batch_synchronize": (I, [VP]),
+        "sadi_batch_destroy": (I, [VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -212,6 +223,114 @@ class Solver:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             _check(load_library().sadi_destroy(self._ctx))
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ---- batches ---------------------------------------------------------------------
+PATHS = {"fft_gs": 0, "dense": 1}
+
+
+class Batch:
+    """Independent problems (own N, alpha, kappa; shared tau, domain, g = -sin u, FP64)
+    advanced together through the batched entry points of include/sadi.h.  The batch
+    runs on its own HIP stream: calls wait for torch's current stream first and the
+    batch is synchronised before results are handed back."""
+
+    def __init__(self, n, alpha, kappa, tau: float, domain: Sequence[float] = (-1.0, 1.0), dense_max_n: int = 1023):
+        lib = load_library()
+        self.n = [int(v) for v in n]
+        cnt = len(self.n)
+        if not (len(alpha) == len(kappa) == cnt):
+            raise ValueError("n, alpha and kappa must have the same length")
+        self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        self.kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        self.tau = float(tau)
+        dom = np.asarray(domain, dtype=np.float64)
+        narr = (ctypes.c_int * cnt)(*self.n)
+        h = ctypes.c_void_p()
+        _check(lib.sadi_batch_create(cnt, narr, _dptr(self.alpha), _dptr(self.kappa), self.tau, _dptr(dom),
+                                     int(dense_max_n), ctypes.byref(h)))
+        self._h = h
+        self._bound = None
+
+    def __len__(self):
+        return len(self.n)
+
+    def bind(self, u_prev, u_cur, phi2=None):
+        """Lists of contiguous float64 (N_i, N_i) CUDA tensors; kept referenced."""
+        cnt = len(self.n)
+        if len(u_prev) != cnt or len(u_cur) != cnt or (phi2 is not None and len(phi2) != cnt):
+            raise ValueError("one tensor per instance expected")
+        arr = ctypes.c_void_p * cnt
+        up = arr(*[_grid_ptr(t, n) for t, n in zip(u_prev, self.n)])
+        uc = arr(*[_grid_ptr(t, n) for t, n in zip(u_cur, self.n)])
+        p2 = arr(*[_grid_ptr(t, n) for t, n in zip(phi2, self.n)]) if phi2 is not None else None
+        _check(load_library().sadi_batch_bind(self._h, up, uc, p2))
+        self._bound = (list(u_prev), list(u_cur), None if phi2 is None else list(phi2))
+
+    def _before(self):
+        import torch
+        torch.cuda.current_stream().synchronize()
+
+    def first_step(self):
+        self._before()
+        _check(load_library().sadi_batch_first_step(self._h))
+        self.synchronize()
+
+    def run(self, nsteps: int, sync: bool = True):
+        self._before()
+        _check(load_library().sadi_batch_run(self._h, int(nsteps)))
+        if sync:
+            self.synchronize()
+
+    def synchronize(self):
+        _check(load_library().sadi_batch_synchronize(self._h))
+
+    def set_graph(self, enable: bool = True):
+        _check(load_library().sadi_batch_set_graph(self._h, 1 if enable else 0))
+
+    def set_path(self, n: int, path: str):
+        _check(load_library().sadi_batch_set_path(self._h, int(n), PATHS[path]))
+
+    def tune(self, steps: int = 5):
+        _check(load_library().sadi_batch_tune(self._h, int(steps)))
+        return self.groups()
+
+    def groups(self):
+        lib = load_library()
+        cnt, ng, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+        _check(lib.sadi_batch_get_info(self._h, ctypes.byref(cnt), ctypes.byref(ng), ctypes.byref(nb)))
+        out = []
+        names = {v: k for k, v in PATHS.items()}
+        for i in range(ng.value):
+            n, mem, path = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            mf, md = ctypes.c_double(), ctypes.c_double()
+            _check(lib.sadi_batch_get_group(self._h, i, ctypes.byref(n), ctypes.byref(mem), ctypes.byref(path),
+                                            ctypes.byref(mf), ctypes.byref(md)))
+            out.append({"n": n.value, "members": mem.value, "path": names[path.value],
+                        "ms_fft_gs": mf.value, "ms_dense": md.value})
+        return out
+
+    def device_bytes(self) -> int:
+        cnt, ng, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+        _check(load_library().sadi_batch_get_info(self._h, ctypes.byref(cnt), ctypes.byref(ng), ctypes.byref(nb)))
+        return nb.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().sadi_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -29,6 +29,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 SOURCES = [
     ("kernels.hip", "hip"),
     ("sadi.cpp", "hip"),
+    ("batch.cpp", "hip"),
     ("setup_math.cpp", "c++"),
 ]
 
@@ -55,7 +56,7 @@ def build(verbose: bool = True) -> str:
         _run(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lrocblas", "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

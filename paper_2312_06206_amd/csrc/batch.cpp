@@ -1,0 +1,512 @@
+// Batched S-ADI: many independent problems (their own N, alpha, kappa) advanced together.
+// Instances are grouped by N; each group runs every phase of a step as one launch over all
+// of its instances (blockIdx.y), and a run of steps can be replayed from a captured HIP
+// graph.  Per group, the two line sweeps take either the Gohberg-Semencul FFT kernels or
+// two dense products with the explicit H^-1 (rocBLAS batched DGEMM); a timing pass picks
+// the faster one.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "context.hpp"
+#include "kernels.hpp"
+
+using namespace sadi_impl;
+
+namespace {
+
+struct Group {
+  int n = 0, m = 0;
+  std::vector<int> members;                   // instance indices
+  sadi::BatchInst* d_inst = nullptr;          // device copy of the members' descriptors
+  sadi::BatchInst* d_scratch_inst = nullptr;  // same, state in scratch buffers (timing)
+  int path = SADI_PATH_FFT_GS;
+  double ms[2] = {-1.0, -1.0};                // timed ms per step for each path
+  // dense path: H^-1 per member and rocBLAS pointer arrays (A = H^-1, B = X, T = S as real)
+  std::vector<double*> hinv;
+  const double** d_hinv = nullptr;
+  const double** d_x_in = nullptr;
+  double** d_x_out = nullptr;
+  const double** d_t_in = nullptr;
+  double** d_t_out = nullptr;
+};
+
+}  // namespace
+
+struct sadi_batch {
+  int magic = 0x5AD2;
+  int count = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  std::vector<sadi_ctx*> ctx;
+  std::vector<double*> u_prev, u_cur;
+  std::vector<const double*> phi2;
+  bool bound = false;
+  std::vector<Group> groups;
+  rocblas_handle blas = nullptr;
+  std::vector<void*> allocs;
+  bool use_graph = false;
+  hipGraphExec_t pair_exec = nullptr;         // two steps n >= 1 of a run (both buffer parities)
+  long long device_bytes = 0;
+
+  sadi_status alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return fail(SADI_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    allocs.push_back(*p);
+    device_bytes += (long long)bytes;
+    return SADI_OK;
+  }
+  void drop_graph() {
+    if (pair_exec) (void)hipGraphExecDestroy(pair_exec);
+    pair_exec = nullptr;
+  }
+};
+
+namespace {
+
+bool batch_ok(const sadi_batch* b) { return b != nullptr && b->magic == 0x5AD2; }
+
+template <int M> struct BRowsFwd {
+  static void run(const sadi_batch* b, const Group& g, const sadi::BatchInst* bi, int lf, int iu, int ip) {
+    const sadi_ctx* c = b->ctx[g.members[0]];
+    sadi::launch_batch_rows_fwd<M>(lf, bi, (int)g.members.size(), iu, ip, c->ldX, c->ldS, g.n, tables(c), b->stream);
+  }
+};
+template <int M> struct BColsConv {
+  static void run(const sadi_batch* b, const Group& g, const sadi::BatchInst* bi) {
+    const sadi_ctx* c = b->ctx[g.members[0]];
+    sadi::launch_batch_cols_conv<M>(bi, (int)g.members.size(), c->ldS, g.n, c->ldlam, tables(c), b->stream);
+  }
+};
+template <int M> struct BRowsRhs {
+  static void run(const sadi_batch* b, const Group& g, const sadi::BatchInst* bi, int mode, int iu) {
+    const sadi_ctx* c = b->ctx[g.members[0]];
+    sadi::launch_batch_rows_rhs<M>(mode, bi, (int)g.members.size(), iu, c->ldS, c->ldX, g.n, tables(c), b->stream);
+  }
+};
+template <int M> struct BColsGS {
+  static void run(const sadi_batch* b, const Group& g, const sadi::BatchInst* bi) {
+    const sadi_ctx* c = b->ctx[g.members[0]];
+    sadi::launch_batch_cols_gs<M>(bi, (int)g.members.size(), c->ldX, g.n, tables(c), b->stream);
+  }
+};
+
+// the two sweeps X <- H^-1 B H^-1 by dense products: in column-major terms the row-major
+// N x N array B (pitch ldX) is B^T, and the x- then y-sweep give T = H^-1 B^T, U^T = T H^-1
+sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
+  const sadi_ctx* c = b->ctx[g.members[0]];
+  const double one = 1.0, zero = 0.0;
+  const int n = g.n, cnt = (int)g.members.size();
+  rocblas_status st = rocblas_dgemm_batched(b->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
+                                            g.d_hinv, n, g.d_x_in, c->ldX, &zero, g.d_t_out, c->ldX, cnt);
+  if (st == rocblas_status_success)
+    st = rocblas_dgemm_batched(b->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, g.d_t_in,
+                               c->ldX, g.d_hinv, n, &zero, g.d_x_out, c->ldX, cnt);
+  if (st != rocblas_status_success)
+    return fail(SADI_E_DEVICE, std::string("rocblas_dgemm_batched: ") + rocblas_status_to_string(st));
+  return SADI_OK;
+}
+
+// one step of every group.  first: start-up step (x0 = u[iu], phi2); otherwise lf selects
+// the deferred update in the row transform (u[ip] <- 2 u[iu] - u[ip] + X, then the step
+// advances u[ip]).  On return X holds each instance's increment.
+sadi_status batch_step(sadi_batch* b, bool scratch, bool first, int lf, int iu, int ip) {
+  for (Group& g : b->groups) {
+    const sadi::BatchInst* bi = scratch ? g.d_scratch_inst : g.d_inst;
+    dispatch_m<BRowsFwd>(g.m, b, g, bi, lf, iu, ip);
+    dispatch_m<BColsConv>(g.m, b, g, bi);
+    const int su = lf ? ip : iu;   // the state this step advances
+    if (g.path == SADI_PATH_FFT_GS) {
+      dispatch_m<BRowsRhs>(g.m, b, g, bi, first ? 1 : 0, su);
+      dispatch_m<BColsGS>(g.m, b, g, bi);
+    } else {
+      dispatch_m<BRowsRhs>(g.m, b, g, bi, first ? 4 : 3, su);
+      sadi_status st = dense_sweeps(b, g);
+      if (st != SADI_OK) return st;
+    }
+  }
+  return check_launch();
+}
+
+sadi_status batch_leapfrog(sadi_batch* b, bool scratch, int mode, int ic, int ip) {
+  for (Group& g : b->groups) {
+    const sadi_ctx* c = b->ctx[g.members[0]];
+    sadi::launch_batch_leapfrog(mode, scratch ? g.d_scratch_inst : g.d_inst, (int)g.members.size(), ic, ip, c->ldX,
+                                g.n, b->stream);
+  }
+  return check_launch();
+}
+
+// nsteps steps n >= 1 from (u[0], u[1]) = (u^{n-1}, u^n); the result is left the same way
+sadi_status batch_run(sadi_batch* b, bool scratch, int nsteps, bool graph) {
+  if (nsteps <= 0) return SADI_OK;
+  sadi_status st = batch_step(b, scratch, false, 0, 1, 0);
+  if (st != SADI_OK) return st;
+  int cur = 1, prev = 0;
+  int left = nsteps - 1;
+  if (graph && !scratch && left >= 2) {
+    if (!b->pair_exec) {
+      // capture two steps (cur = 1, then cur = 0): the buffer roles repeat every two steps
+      hipGraph_t gr = nullptr;
+      SADI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      sadi_status s1 = batch_step(b, false, false, 1, 1, 0);
+      sadi_status s2 = s1 == SADI_OK ? batch_step(b, false, false, 1, 0, 1) : s1;
+      hipError_t e = hipStreamEndCapture(b->stream, &gr);
+      if (s2 != SADI_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return s2;
+      }
+      if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->pair_exec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) {
+        b->pair_exec = nullptr;
+        return fail(SADI_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    }
+    for (; left >= 2; left -= 2) SADI_HIP(hipGraphLaunch(b->pair_exec, b->stream));
+  }
+  for (; left > 0; --left) {
+    st = batch_step(b, scratch, false, 1, cur, prev);
+    if (st != SADI_OK) return st;
+    std::swap(cur, prev);
+  }
+  // pending: newest = 2 u[cur] - u[prev] + X; leave it in u[1], the step before in u[0]
+  return cur == 1 ? batch_leapfrog(b, scratch, 2, 1, 0) : batch_leapfrog(b, scratch, 0, 0, 1);
+}
+
+sadi_status upload_desc(sadi_batch* b, Group& g, bool scratch, const std::vector<double*>& s0,
+                        const std::vector<double*>& s1) {
+  std::vector<sadi::BatchInst> h(g.members.size());
+  for (size_t k = 0; k < g.members.size(); ++k) {
+    const int i = g.members[k];
+    const sadi_ctx* c = b->ctx[i];
+    sadi::BatchInst& d = h[k];
+    d.u[0] = s0[k];
+    d.u[1] = s1[k];
+    d.phi2 = scratch ? s0[k] : b->phi2[i];
+    d.S = c->S;
+    d.X = c->X;
+    d.lam2d = c->lam2d;
+    d.lam_s = c->lam_s;
+    d.lam_c = c->lam_c;
+    d.f = c->f;
+    d.sc = scalars(c, false);
+  }
+  sadi::BatchInst* dst = scratch ? g.d_scratch_inst : g.d_inst;
+  SADI_HIP(hipMemcpy(dst, h.data(), sizeof(sadi::BatchInst) * h.size(), hipMemcpyHostToDevice));
+  return SADI_OK;
+}
+
+// start-up step uses the scalars of the first step (w = 1/2); they differ only by that factor
+sadi_status set_scalars(sadi_batch* b, Group& g, bool first) {
+  std::vector<sadi::BatchInst> h(g.members.size());
+  SADI_HIP(hipMemcpy(h.data(), g.d_inst, sizeof(sadi::BatchInst) * h.size(), hipMemcpyDeviceToHost));
+  for (size_t k = 0; k < g.members.size(); ++k) h[k].sc = scalars(b->ctx[g.members[k]], first);
+  SADI_HIP(hipMemcpy(g.d_inst, h.data(), sizeof(sadi::BatchInst) * h.size(), hipMemcpyHostToDevice));
+  return SADI_OK;
+}
+
+void destroy_batch(sadi_batch* b) {
+  b->drop_graph();
+  if (b->blas) (void)rocblas_destroy_handle(b->blas);
+  for (void* p : b->allocs) (void)hipFree(p);
+  for (sadi_ctx* c : b->ctx)
+    if (c) (void)sadi_destroy(c);
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  b->magic = 0;
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+sadi_status sadi_batch_create(int count, const int* n, const double* alpha, const double* kappa, double tau,
+                              const double* domain, int dense_max_n, sadi_batch** out) {
+  if (!out) return fail(SADI_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (count <= 0) return fail(SADI_E_INVALID, "count must be positive");
+  if (!n || !alpha || !kappa || !domain) return fail(SADI_E_INVALID, "NULL array");
+  for (int i = 0; i < count; ++i) {
+    sadi_status st = validate_problem(alpha[i], kappa[i], n[i], tau, domain, false);
+    if (st != SADI_OK) return fail(st, std::string("instance ") + std::to_string(i) + ": " + sadi_last_error());
+  }
+  sadi_batch* b = new (std::nothrow) sadi_batch;
+  if (!b) return fail(SADI_E_NOMEM, "host allocation");
+  auto bail = [&](sadi_status st) {
+    const std::string msg = sadi_last_error();
+    destroy_batch(b);
+    return fail(st, msg);
+  };
+  b->count = count;
+  b->ctx.assign(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    sadi_status st = sadi_setup(alpha[i], kappa[i], n[i], tau, domain, &b->ctx[i]);
+    if (st != SADI_OK) {
+      const std::string msg = std::string("instance ") + std::to_string(i) + ": " + sadi_last_error();
+      destroy_batch(b);
+      return fail(st, msg);
+    }
+  }
+  if (hipStreamCreate(&b->own_stream) != hipSuccess) {
+    b->own_stream = nullptr;
+    return bail(fail(SADI_E_DEVICE, "hipStreamCreate"));
+  }
+  b->stream = b->own_stream;
+  for (sadi_ctx* c : b->ctx) c->stream = b->stream;
+  if (rocblas_create_handle(&b->blas) != rocblas_status_success) {
+    b->blas = nullptr;
+    return bail(fail(SADI_E_DEVICE, "rocblas_create_handle"));
+  }
+  (void)rocblas_set_stream(b->blas, b->stream);
+  (void)rocblas_set_pointer_mode(b->blas, rocblas_pointer_mode_host);
+
+  std::map<int, int> by_n;
+  for (int i = 0; i < count; ++i) {
+    auto it = by_n.find(n[i]);
+    if (it == by_n.end()) {
+      by_n[n[i]] = (int)b->groups.size();
+      Group g;
+      g.n = n[i];
+      g.m = n[i] + 1;
+      b->groups.push_back(g);
+      b->groups.back().members.push_back(i);
+    } else {
+      b->groups[it->second].members.push_back(i);
+    }
+  }
+  for (Group& g : b->groups) {
+    const size_t cnt = g.members.size();
+    sadi_status st;
+    if ((st = b->alloc((void**)&g.d_inst, sizeof(sadi::BatchInst) * cnt)) != SADI_OK) return bail(st);
+    if ((st = b->alloc((void**)&g.d_scratch_inst, sizeof(sadi::BatchInst) * cnt)) != SADI_OK) return bail(st);
+    if (g.n > dense_max_n) continue;
+    // explicit H^-1 of every member: the line solve applied to the rows of the identity
+    const size_t nn = (size_t)g.n * g.n;
+    std::vector<double> eye(nn, 0.0);
+    for (int j = 0; j < g.n; ++j) eye[(size_t)j * g.n + j] = 1.0;
+    g.hinv.resize(cnt);
+    std::vector<const double*> ha(cnt), hx(cnt), ht(cnt);
+    for (size_t k = 0; k < cnt; ++k) {
+      sadi_ctx* c = b->ctx[g.members[k]];
+      if ((st = b->alloc((void**)&g.hinv[k], sizeof(double) * nn)) != SADI_OK) return bail(st);
+      if (hipMemcpy(g.hinv[k], eye.data(), sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(SADI_E_DEVICE, "hipMemcpy"));
+      if ((st = sadi_toeplitz_solve(c, g.hinv[k], g.n, g.n)) != SADI_OK) return bail(st);
+      ha[k] = g.hinv[k];
+      hx[k] = c->X;
+      ht[k] = reinterpret_cast<const double*>(c->S);   // N x ldX doubles fit in the spectrum buffer
+    }
+    const size_t pb = sizeof(double*) * cnt;
+    if ((st = b->alloc((void**)&g.d_hinv, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_x_in, pb)) != SADI_OK ||
+        (st = b->alloc((void**)&g.d_x_out, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_t_in, pb)) != SADI_OK ||
+        (st = b->alloc((void**)&g.d_t_out, pb)) != SADI_OK)
+      return bail(st);
+    if (hipMemcpy(g.d_hinv, ha.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_x_in, hx.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_x_out, hx.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_t_in, ht.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_t_out, ht.data(), pb, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(SADI_E_DEVICE, "hipMemcpy"));
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(SADI_E_DEVICE, "setup synchronisation"));
+  *out = b;
+  return SADI_OK;
+}
+
+sadi_status sadi_batch_bind(sadi_batch* b, double* const* u_prev, double* const* u_cur, const double* const* phi2) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (!u_prev || !u_cur) return fail(SADI_E_INVALID, "NULL array");
+  for (int i = 0; i < b->count; ++i) {
+    if (!u_prev[i] || !u_cur[i]) return fail(SADI_E_INVALID, "NULL state pointer for instance " + std::to_string(i));
+    if (u_prev[i] == u_cur[i]) return fail(SADI_E_INVALID, "u_prev and u_cur alias for instance " + std::to_string(i));
+  }
+  b->u_prev.assign(u_prev, u_prev + b->count);
+  b->u_cur.assign(u_cur, u_cur + b->count);
+  b->phi2.assign(b->count, nullptr);
+  if (phi2)
+    for (int i = 0; i < b->count; ++i) b->phi2[i] = phi2[i];
+  for (Group& g : b->groups) {
+    std::vector<double*> s0, s1;
+    for (int i : g.members) {
+      s0.push_back(b->u_prev[i]);
+      s1.push_back(b->u_cur[i]);
+    }
+    sadi_status st = upload_desc(b, g, false, s0, s1);
+    if (st != SADI_OK) return st;
+  }
+  b->drop_graph();
+  b->bound = true;
+  return SADI_OK;
+}
+
+sadi_status sadi_batch_first_step(sadi_batch* b) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (!b->bound) return fail(SADI_E_STATE, "no state bound");
+  for (int i = 0; i < b->count; ++i)
+    if (!b->phi2[i]) return fail(SADI_E_INVALID, "no phi2 bound for instance " + std::to_string(i));
+  for (Group& g : b->groups) {
+    sadi_status st = set_scalars(b, g, true);
+    if (st != SADI_OK) return st;
+  }
+  sadi_status st = batch_step(b, false, true, 0, 0, 1);
+  if (st == SADI_OK) st = batch_leapfrog(b, false, 1, 0, 1);
+  for (Group& g : b->groups) {
+    sadi_status s2 = set_scalars(b, g, false);
+    if (st == SADI_OK) st = s2;
+  }
+  return st;
+}
+
+sadi_status sadi_batch_run(sadi_batch* b, int nsteps) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (!b->bound) return fail(SADI_E_STATE, "no state bound");
+  if (nsteps < 0) return fail(SADI_E_INVALID, "nsteps must be >= 0");
+  return batch_run(b, false, nsteps, b->use_graph);
+}
+
+sadi_status sadi_batch_set_graph(sadi_batch* b, int enable) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  b->use_graph = enable != 0;
+  if (!b->use_graph) b->drop_graph();
+  return SADI_OK;
+}
+
+sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (path != SADI_PATH_FFT_GS && path != SADI_PATH_DENSE) return fail(SADI_E_INVALID, "unknown path");
+  for (Group& g : b->groups) {
+    if (g.n != n) continue;
+    if (path == SADI_PATH_DENSE && g.hinv.empty())
+      return fail(SADI_E_UNSUPPORTED, "no explicit inverse for N = " + std::to_string(n) + " (above dense_max_n)");
+    g.path = path;
+    b->drop_graph();
+    return SADI_OK;
+  }
+  return fail(SADI_E_INVALID, "no instance with N = " + std::to_string(n));
+}
+
+sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (steps < 1) return fail(SADI_E_INVALID, "steps must be >= 1");
+  // scratch state (zeros) so that the caller's state is untouched
+  std::vector<void*> tmp;
+  auto cleanup = [&]() {
+    for (void* p : tmp) (void)hipFree(p);
+  };
+  for (Group& g : b->groups) {
+    std::vector<double*> s0, s1;
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      void* p0 = nullptr;
+      void* p1 = nullptr;
+      const size_t bytes = sizeof(double) * (size_t)g.n * g.n;
+      if (hipMalloc(&p0, bytes) != hipSuccess || hipMalloc(&p1, bytes) != hipSuccess) {
+        if (p0) (void)hipFree(p0);
+        cleanup();
+        return fail(SADI_E_NOMEM, "tuning scratch state");
+      }
+      tmp.push_back(p0);
+      tmp.push_back(p1);
+      (void)hipMemset(p0, 0, bytes);
+      (void)hipMemset(p1, 0, bytes);
+      s0.push_back((double*)p0);
+      s1.push_back((double*)p1);
+    }
+    sadi_status st = upload_desc(b, g, true, s0, s1);
+    if (st != SADI_OK) {
+      cleanup();
+      return st;
+    }
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(SADI_E_DEVICE, "hipEventCreate");
+  }
+  const std::vector<int> saved = [&] {
+    std::vector<int> v;
+    for (Group& g : b->groups) v.push_back(g.path);
+    return v;
+  }();
+  sadi_status st = SADI_OK;
+  // time each group alone: the other groups are skipped by moving them out temporarily
+  std::vector<Group> all;
+  all.swap(b->groups);
+  for (size_t gi = 0; gi < all.size() && st == SADI_OK; ++gi) {
+    b->groups.assign(1, all[gi]);
+    for (int path = 0; path < 2 && st == SADI_OK; ++path) {
+      if (path == SADI_PATH_DENSE && all[gi].hinv.empty()) continue;
+      b->groups[0].path = path;
+      st = batch_run(b, true, 2, false);   // warm-up
+      if (st != SADI_OK) break;
+      (void)hipEventRecord(e0, b->stream);
+      st = batch_run(b, true, steps, false);
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(SADI_E_DEVICE, "tuning run");
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      all[gi].ms[path] = ms / steps;
+    }
+    b->groups.clear();
+  }
+  b->groups.swap(all);
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    Group& g = b->groups[gi];
+    g.path = saved[gi];
+    if (st == SADI_OK)
+      g.path = (g.ms[SADI_PATH_DENSE] >= 0.0 && g.ms[SADI_PATH_DENSE] < g.ms[SADI_PATH_FFT_GS]) ? SADI_PATH_DENSE
+                                                                                                 : SADI_PATH_FFT_GS;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(b->stream);
+  cleanup();
+  b->drop_graph();
+  return st;
+}
+
+sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,
+                                 double* ms_dense) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (index < 0 || index >= (int)b->groups.size()) return fail(SADI_E_INVALID, "group index out of range");
+  const Group& g = b->groups[index];
+  if (n) *n = g.n;
+  if (members) *members = (int)g.members.size();
+  if (path) *path = g.path;
+  if (ms_fft) *ms_fft = g.ms[SADI_PATH_FFT_GS];
+  if (ms_dense) *ms_dense = g.ms[SADI_PATH_DENSE];
+  return SADI_OK;
+}
+
+sadi_status sadi_batch_get_info(const sadi_batch* b, int* count, int* groups, long long* bytes) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  long long total = b->device_bytes;
+  for (const sadi_ctx* c : b->ctx) total += c->device_bytes;
+  if (count) *count = b->count;
+  if (groups) *groups = (int)b->groups.size();
+  if (bytes) *bytes = total;
+  return SADI_OK;
+}
+
+sadi_status sadi_batch_synchronize(sadi_batch* b) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  SADI_HIP(hipStreamSynchronize(b->stream));
+  return SADI_OK;
+}
+
+sadi_status sadi_batch_destroy(sadi_batch* b) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  (void)hipStreamSynchronize(b->stream);
+  destroy_batch(b);
+  return SADI_OK;
+}
+
+}  // extern "C"

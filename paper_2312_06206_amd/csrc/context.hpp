@@ -1,0 +1,160 @@
+// Internal: the solver context and helpers shared by the single-instance and the
+// batched entry points.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <initializer_list>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sadi.h"
+#include "kernels.hpp"
+
+namespace sadi_impl {
+// record msg as the calling thread's last error and return st
+sadi_status fail(sadi_status st, const std::string& msg);
+sadi_status check_launch();
+bool finite_all(std::initializer_list<double> v);
+bool supported_n(int n);
+// argument checks of sadi_setup (allow2: alpha = 2 accepted, for injected tables)
+sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2);
+}  // namespace sadi_impl
+
+#define SADI_HIP(call)                                                                                  \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      return sadi_impl::fail(SADI_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+struct sadi_ctx {
+  int n = 0, m = 0;
+  double alpha = 0, kappa = 0, tau = 0, a = 0, b = 0, h = 0, h_alpha = 0, beta = 0;
+  sadi_g_kind g = SADI_G_NEG_SIN;
+  double g_param = 0.0;
+  sadi_precision prec = SADI_FP64;
+  hipStream_t stream = nullptr;
+  int magic = 0x5AD1;
+  long long device_bytes = 0;
+
+  // device data
+  double2* rootM = nullptr;    // T entries
+  double2* rootS = nullptr;    // E entries
+  double2* root2M = nullptr;   // M entries, e^{-2 pi i k / 2M}
+  double2* lam_s = nullptr;
+  double2* lam_c = nullptr;
+  double* f = nullptr;         // N
+  double* lam2d = nullptr;     // (M+1) rows x ldlam
+  int ldlam = 0;
+  double2* S = nullptr;        // N rows x ldS complex
+  int ldS = 0;
+  double* X = nullptr;         // N rows x ldX
+  int ldX = 0;
+  // mixed precision: FP32 copies of the FFT and Gohberg-Semencul tables, FP64 eigenvalues
+  // of the 2M-circulant embedding of beta T(a) (even / odd frequencies, scaled by 1/(2M))
+  float2* rootM32 = nullptr;
+  float2* rootS32 = nullptr;
+  float2* q32 = nullptr;
+  float2* lam_s32 = nullptr;
+  float2* lam_c32 = nullptr;
+  float* f32 = nullptr;
+  double* sig_e = nullptr;
+  double* sig_o = nullptr;
+
+  std::vector<void*> allocs;
+
+  // per-kernel timing: events[5*s + k] precedes kernel k of timed step s (k = 4: end)
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  int timed_steps = 0;
+  static constexpr int kMaxTimedSteps = 8192;
+
+  sadi_status alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return sadi_impl::fail(SADI_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    allocs.push_back(*p);
+    device_bytes += (long long)bytes;
+    return SADI_OK;
+  }
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
+  }
+  // event k of the current timed step (creating it on demand); null when not timing
+  hipEvent_t mark(int k) {
+    if (!timing || timed_steps >= kMaxTimedSteps) return nullptr;
+    const size_t idx = (size_t)timed_steps * 5 + k;
+    while (events.size() <= idx) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      events.push_back(e);
+    }
+    return events[idx];
+  }
+};
+
+namespace sadi_impl {
+
+inline bool ctx_ok(const sadi_ctx* c) { return c != nullptr && c->magic == 0x5AD1; }
+
+// ---------------------------------------------------------------------------------
+// dispatch on M
+template <template <int> class F, class... A>
+void dispatch_m(int m, A&&... args) {
+  switch (m) {
+#define SADI_CASE(MM) \
+  case MM:            \
+    F<MM>::run(std::forward<A>(args)...); \
+    break;
+    SADI_FOR_EACH_M(SADI_CASE)
+#undef SADI_CASE
+    default:
+      break;
+  }
+}
+
+template <int M> int threads_per_line() { return M / sadi::Shape<M>::E; }
+template <int M> int e_of() { return sadi::Shape<M>::E; }
+template <int M> int p2_of() { return sadi::Shape<M>::P2; }
+
+struct ShapeInfo {
+  int E, P2, T;
+};
+inline ShapeInfo shape_of(int m) {
+  switch (m) {
+#define SADI_SH(MM) \
+  case MM:          \
+    return ShapeInfo{sadi::Shape<MM>::E, sadi::Shape<MM>::P2, MM / sadi::Shape<MM>::E};
+    SADI_FOR_EACH_M(SADI_SH)
+#undef SADI_SH
+    default:
+      return ShapeInfo{0, 0, 0};
+  }
+}
+
+inline sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS, c->root2M}; }
+inline sadi::GSTables64 gs_tables(const sadi_ctx* c) {
+  return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f};
+}
+
+
+inline sadi::StepScalars scalars(const sadi_ctx* c, bool first) {
+  sadi::StepScalars sc{};
+  const double t2 = c->tau * c->tau;
+  const double w = first ? 0.5 : 1.0;
+  sc.sigma = -w * t2 * c->kappa * c->h_alpha;   // h_alpha = h^-alpha
+  sc.gamma = w * t2;
+  sc.tau = c->tau;
+  sc.gkind = (int)c->g;
+  sc.gparam = c->g_param;
+  return sc;
+}
+
+}  // namespace sadi_impl

@@ -251,8 +251,7 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
 // LF = 1 first completes the previous step's update: u = 2 u + (-uprev) + hat, with
 // u = ucur, hat = the increment left in X by the y-sweep; the result overwrites uprev.
 template <int M, int LF>
-__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
-rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
+__device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
   using L_t = typename RowCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
@@ -354,8 +353,7 @@ __device__ __forceinline__ void shift_odd_slots(VV* d, bool odd, std::integer_se
 // into its even and odd frequencies (two length-M transforms of c and W_P^y c), each
 // handled by its own line of the workgroup (lines 2g / 2g+1 for column group g).
 template <int M>
-__global__ void __launch_bounds__(ColConvCfg<M>::NT) SADI_OCC4
-cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
+__device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
                  FFTTables<double> tab, const V* __restrict__ root2M, int ngroups) {
   using Cfg = ColConvCfg<M>;
   using L_t = typename Cfg::Line;
@@ -521,8 +519,7 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
 }
 
 template <int M, int MODE>
-__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
-rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
+__device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
   using L_t = typename RowCfg<M>::Line;
@@ -533,11 +530,13 @@ rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__
   const bool live = y < n;
   const int yy = live ? y : 0;
   double* xo = X + (size_t)yy * ldx;
+  // MODE 3 / 4: as 0 / 1 but X = B (no line solve; the dense-inverse path follows)
+  constexpr int RMODE = MODE >= 3 ? MODE - 3 : MODE;
   V d[E];
-  if (!rhs_phase<MODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
-                       MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M))
+  if (!rhs_phase<RMODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
+                        RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M))
     return;
-  gs_solve(L, d, smem, tab, gs);
+  if constexpr (MODE < 3) gs_solve(L, d, smem, tab, gs);
   if (live) {
     // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
 #pragma unroll
@@ -594,8 +593,7 @@ rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<
 // cols_gs: y-line solves on the columns of X and the leapfrog update.
 // MODE 0: uout = 2 ucur - uprev + Uhat (uout may alias uprev); MODE 1: uout = ucur + Uhat.
 template <int M, int MODE>
-__global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
-cols_gs_kernel(double* X, int ldx, const double* ucur, const double* uprev,
+__device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* ucur, const double* uprev,
                double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
   using Cfg = ColGSCfg<M>;
   using L_t = typename Cfg::Line;
@@ -686,6 +684,92 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
         if constexpr (MODE == 0) (uout + T * m * ldu)[o] = 2.0 * uc - (uprev + T * m * ldu)[o] + d[m].x;
         else (uout + T * m * ldu)[o] = uc + d[m].x;
       }
+    }
+  }
+}
+
+
+// ----------------------------------------------------------------------------------
+// kernels: one instance (pointer arguments) and batched (instance blockIdx.y of an
+// array of BatchInst sharing N, pitches and line tables; iu / ip pick the state buffers)
+template <int M, int LF>
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
+                int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
+  rows_fwd_body<M, LF>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M);
+}
+template <int M, int LF>
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+rows_fwd_batched(const BatchInst* __restrict__ bi, int iu, int ip, int ldx, int lds_, int n, FFTTables<double> tab) {
+  const BatchInst& p = bi[blockIdx.y];
+  rows_fwd_body<M, LF>(p.u[iu], p.u[ip], p.X, ldx, n, p.S, lds_, n, tab, tab.root2M);
+}
+
+template <int M>
+__global__ void __launch_bounds__(ColConvCfg<M>::NT) SADI_OCC4
+cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
+                 FFTTables<double> tab, const V* __restrict__ root2M, int ngroups) {
+  cols_conv_body<M>(S, lds_, n, lam, ldlam, tab, root2M, ngroups);
+}
+template <int M>
+__global__ void __launch_bounds__(ColConvCfg<M>::NT) SADI_OCC4
+cols_conv_batched(const BatchInst* __restrict__ bi, int lds_, int n, int ldlam, FFTTables<double> tab, int ngroups) {
+  const BatchInst& p = bi[blockIdx.y];
+  cols_conv_body<M>(p.S, lds_, n, p.lam2d, ldlam, tab, tab.root2M, ngroups);
+}
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
+                   const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
+                   StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
+  rows_rhs_gs_body<M, MODE>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M);
+}
+template <int M, int MODE>
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+rows_rhs_gs_batched(const BatchInst* __restrict__ bi, int iu, int lds_, int ldx, int n, FFTTables<double> tab) {
+  const BatchInst& p = bi[blockIdx.y];
+  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f};
+  rows_rhs_gs_body<M, MODE>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M);
+}
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
+cols_gs_kernel(double* X, int ldx, const double* ucur, const double* uprev,
+               double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
+  cols_gs_body<M, MODE>(X, ldx, ucur, uprev, uout, ldu, n, tab, gs, ngroups);
+}
+template <int M>
+__global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
+cols_gs_batched(const BatchInst* __restrict__ bi, int ldx, int n, FFTTables<double> tab, int ngroups) {
+  const BatchInst& p = bi[blockIdx.y];
+  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f};
+  cols_gs_body<M, 2>(p.X, ldx, nullptr, nullptr, nullptr, n, n, tab, gs, ngroups);
+}
+
+// batched update, instance blockIdx.z, row blockIdx.y:
+//   mode 0: u[ip] = 2 u[ic] - u[ip] + X       (newest in the former previous buffer)
+//   mode 1: u[ip] = u[ic] + X                 (start-up step)
+//   mode 2: u[ic], u[ip] = 2 u[ic] - u[ip] + X, u[ic]   (newest in the current buffer)
+__global__ void __launch_bounds__(256)
+leapfrog_batched(const BatchInst* __restrict__ bi, int mode, int ic, int ip, int ldx, int n) {
+  const BatchInst& p = bi[blockIdx.z];
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (i >= n) return;
+  const size_t o = (size_t)j * n + i;
+  double* uc = p.u[ic];
+  double* up = p.u[ip];
+  const double h = p.X[(size_t)j * ldx + i];
+  const double c = uc[o];
+  if (mode == 1) {
+    up[o] = c + h;
+  } else {
+    const double v = 2.0 * c - up[o] + h;
+    if (mode == 0) {
+      up[o] = v;
+    } else {
+      up[o] = c;
+      uc[o] = v;
     }
   }
 }
@@ -804,6 +888,52 @@ void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur
                        uout, ldu, n, tab, mx, ngroups);
 }
 
+
+// ---- batched launchers
+template <int M>
+void launch_batch_rows_fwd(int lf, const BatchInst* bi, int count, int iu, int ip, int ldx, int lds_, int n,
+                           const FFTTables<double>& tab, hipStream_t st) {
+  const dim3 grid((n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW, count);
+  if (lf)
+    hipLaunchKernelGGL((rows_fwd_batched<M, 1>), grid, dim3(RowCfg<M>::NT), 0, st, bi, iu, ip, ldx, lds_, n, tab);
+  else
+    hipLaunchKernelGGL((rows_fwd_batched<M, 0>), grid, dim3(RowCfg<M>::NT), 0, st, bi, iu, ip, ldx, lds_, n, tab);
+}
+
+template <int M>
+void launch_batch_cols_conv(const BatchInst* bi, int count, int lds_, int n, int ldlam, const FFTTables<double>& tab,
+                            hipStream_t st) {
+  constexpr int CPW = ColConvCfg<M>::LPW / 2;
+  const int ngroups = (M + 1 + CPW - 1) / CPW;
+  const dim3 grid(((ngroups + 7) / 8) * 8, count);
+  hipLaunchKernelGGL(cols_conv_batched<M>, grid, dim3(ColConvCfg<M>::NT), 0, st, bi, lds_, n, ldlam, tab, ngroups);
+}
+
+template <int M>
+void launch_batch_rows_rhs(int mode, const BatchInst* bi, int count, int iu, int lds_, int ldx, int n,
+                           const FFTTables<double>& tab, hipStream_t st) {
+  const dim3 grid((n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW, count);
+  const dim3 blk(RowCfg<M>::NT);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((rows_rhs_gs_batched<M, 0>), grid, blk, 0, st, bi, iu, lds_, ldx, n, tab); break;
+    case 1: hipLaunchKernelGGL((rows_rhs_gs_batched<M, 1>), grid, blk, 0, st, bi, iu, lds_, ldx, n, tab); break;
+    case 3: hipLaunchKernelGGL((rows_rhs_gs_batched<M, 3>), grid, blk, 0, st, bi, iu, lds_, ldx, n, tab); break;
+    default: hipLaunchKernelGGL((rows_rhs_gs_batched<M, 4>), grid, blk, 0, st, bi, iu, lds_, ldx, n, tab); break;
+  }
+}
+
+template <int M>
+void launch_batch_cols_gs(const BatchInst* bi, int count, int ldx, int n, const FFTTables<double>& tab,
+                          hipStream_t st) {
+  const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
+  const dim3 grid(((ngroups + 7) / 8) * 8, count);
+  hipLaunchKernelGGL(cols_gs_batched<M>, grid, dim3(ColGSCfg<M>::NT), 0, st, bi, ldx, n, tab, ngroups);
+}
+
+void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int ip, int ldx, int n, hipStream_t st) {
+  hipLaunchKernelGGL(leapfrog_batched, dim3((n + 255) / 256, n, count), dim3(256), 0, st, bi, mode, ic, ip, ldx, n);
+}
+
 #define SADI_INSTANTIATE(M)                                                                                      \
   template void launch_rows_fwd<M>(const double*, double*, const double*, int, int, V*, int, int,              \
                                    const FFTTables<double>&, const V*, hipStream_t);                             \
@@ -822,7 +952,14 @@ void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur
   template void launch_rows_gs_mixed<M>(double*, int, int, int, const FFTTables<double>&, const MixedTables&,     \
                                         hipStream_t);                                                            \
   template void launch_cols_gs_mixed<M>(int, const double*, int, const double*, const double*, double*, int, int, \
-                                        const FFTTables<double>&, const MixedTables&, hipStream_t);
+                                        const FFTTables<double>&, const MixedTables&, hipStream_t);                \
+  template void launch_batch_rows_fwd<M>(int, const BatchInst*, int, int, int, int, int, int,                     \
+                                         const FFTTables<double>&, hipStream_t);                                  \
+  template void launch_batch_cols_conv<M>(const BatchInst*, int, int, int, int, const FFTTables<double>&,         \
+                                          hipStream_t);                                                           \
+  template void launch_batch_rows_rhs<M>(int, const BatchInst*, int, int, int, int, int, const FFTTables<double>&, \
+                                         hipStream_t);                                                            \
+  template void launch_batch_cols_gs<M>(const BatchInst*, int, int, int, const FFTTables<double>&, hipStream_t);
 
 SADI_FOR_EACH_M(SADI_INSTANTIATE)
 

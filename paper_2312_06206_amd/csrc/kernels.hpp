@@ -145,6 +145,20 @@ struct MixedTables {
   int refine;              // 1: one FP64 residual correction
 };
 
+// One instance of a batch.  The instances of one launch share N, the pitches of S, X and
+// Lambda, and the FFT tables (rootM, rootS, root2M; root2M also serves as Q).
+struct BatchInst {
+  double* u[2];             // the two state buffers, N x N (pitch N), caller-owned
+  const double* phi2;       // start-up velocity, N x N, or null
+  double2* S;               // half spectrum, N rows
+  double* X;                // line-solve workspace, N rows
+  const double* lam2d;      // BCCB eigenvalues, M + 1 rows
+  const double2* lam_s;     // Gohberg-Semencul tables of this instance's H
+  const double2* lam_c;
+  const double* f;
+  StepScalars sc;           // sigma, gamma carry this instance's kappa, h^-alpha, tau
+};
+
 // hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev)
 template <int M>
 void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, double2* S, int lds_,
@@ -164,6 +178,22 @@ void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<do
 template <int M>
 void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                     int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
+// batched forms (instances in blockIdx.y; iu / ip select u[0] or u[1]).  Row pass modes:
+// 0 / 1 step / start-up with the x-sweep, 3 / 4 the same without it (X = B)
+template <int M>
+void launch_batch_rows_fwd(int lf, const BatchInst* bi, int count, int iu, int ip, int ldx, int lds_, int n,
+                           const FFTTables<double>& tab, hipStream_t st);
+template <int M>
+void launch_batch_cols_conv(const BatchInst* bi, int count, int lds_, int n, int ldlam, const FFTTables<double>& tab,
+                            hipStream_t st);
+template <int M>
+void launch_batch_rows_rhs(int mode, const BatchInst* bi, int count, int iu, int lds_, int ldx, int n,
+                           const FFTTables<double>& tab, hipStream_t st);
+template <int M>
+void launch_batch_cols_gs(const BatchInst* bi, int count, int ldx, int n, const FFTTables<double>& tab,
+                          hipStream_t st);
+void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int ip, int ldx, int n, hipStream_t st);
+
 template <int M>
 void launch_rows_rhs_mixed(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2,
                            double* X, int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab,

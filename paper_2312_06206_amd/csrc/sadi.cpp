@@ -11,10 +11,11 @@
 #include <string>
 #include <vector>
 
+#include "context.hpp"
 #include "kernels.hpp"
 #include "setup_math.hpp"
 
-namespace {
+namespace sadi_impl {
 
 thread_local std::string g_last_error;
 
@@ -23,11 +24,11 @@ sadi_status fail(sadi_status st, const std::string& msg) {
   return st;
 }
 
-#define SADI_HIP(call)                                                                    \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) return fail(SADI_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+sadi_status check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return SADI_OK;
+}
 
 bool finite_all(std::initializer_list<double> v) {
   for (double x : v)
@@ -40,122 +41,25 @@ bool supported_n(int n) {
   return m >= 16 && m <= 4096 && (m & (m - 1)) == 0;
 }
 
-}  // namespace
+sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2) {
+  if (!domain) return fail(SADI_E_INVALID, "domain is NULL");
+  if (!finite_all({alpha, kappa, tau, domain[0], domain[1]}))
+    return fail(SADI_E_INVALID, "non-finite parameter");
+  if (!(alpha > 1.0 && (alpha < 2.0 || (allow2 && alpha <= 2.0))))
+    return fail(SADI_E_INVALID, "alpha must lie in (1, 2)");
+  if (!(kappa > 0.0)) return fail(SADI_E_INVALID, "kappa must be positive");
+  if (!(tau > 0.0)) return fail(SADI_E_INVALID, "tau must be positive");
+  if (!(domain[1] > domain[0])) return fail(SADI_E_INVALID, "domain must satisfy b > a");
+  if (n < 1) return fail(SADI_E_INVALID, "N must be >= 1");
+  if (!supported_n(n)) return fail(SADI_E_UNSUPPORTED, "N + 1 must be a power of two in [16, 4096]");
+  return SADI_OK;
+}
 
-struct sadi_ctx {
-  int n = 0, m = 0;
-  double alpha = 0, kappa = 0, tau = 0, a = 0, b = 0, h = 0, h_alpha = 0, beta = 0;
-  sadi_g_kind g = SADI_G_NEG_SIN;
-  double g_param = 0.0;
-  sadi_precision prec = SADI_FP64;
-  hipStream_t stream = nullptr;
-  int magic = 0x5AD1;
-  long long device_bytes = 0;
+}  // namespace sadi_impl
 
-  // device data
-  double2* rootM = nullptr;    // T entries
-  double2* rootS = nullptr;    // E entries
-  double2* root2M = nullptr;   // M entries, e^{-2 pi i k / 2M}
-  double2* lam_s = nullptr;
-  double2* lam_c = nullptr;
-  double* f = nullptr;         // N
-  double* lam2d = nullptr;     // (M+1) rows x ldlam
-  int ldlam = 0;
-  double2* S = nullptr;        // N rows x ldS complex
-  int ldS = 0;
-  double* X = nullptr;         // N rows x ldX
-  int ldX = 0;
-  // mixed precision: FP32 copies of the FFT and Gohberg-Semencul tables, FP64 eigenvalues
-  // of the 2M-circulant embedding of beta T(a) (even / odd frequencies, scaled by 1/(2M))
-  float2* rootM32 = nullptr;
-  float2* rootS32 = nullptr;
-  float2* q32 = nullptr;
-  float2* lam_s32 = nullptr;
-  float2* lam_c32 = nullptr;
-  float* f32 = nullptr;
-  double* sig_e = nullptr;
-  double* sig_o = nullptr;
-
-  std::vector<void*> allocs;
-
-  // per-kernel timing: events[5*s + k] precedes kernel k of timed step s (k = 4: end)
-  bool timing = false;
-  std::vector<hipEvent_t> events;
-  int timed_steps = 0;
-  static constexpr int kMaxTimedSteps = 8192;
-
-  sadi_status alloc(void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-      *p = nullptr;
-      return fail(SADI_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
-    }
-    allocs.push_back(*p);
-    device_bytes += (long long)bytes;
-    return SADI_OK;
-  }
-  void release() {
-    for (void* p : allocs) (void)hipFree(p);
-    allocs.clear();
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    events.clear();
-  }
-  // event k of the current timed step (creating it on demand); null when not timing
-  hipEvent_t mark(int k) {
-    if (!timing || timed_steps >= kMaxTimedSteps) return nullptr;
-    const size_t idx = (size_t)timed_steps * 5 + k;
-    while (events.size() <= idx) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      events.push_back(e);
-    }
-    return events[idx];
-  }
-};
+using namespace sadi_impl;
 
 namespace {
-
-bool ctx_ok(const sadi_ctx* c) { return c != nullptr && c->magic == 0x5AD1; }
-
-// ---------------------------------------------------------------------------------
-// dispatch on M
-template <template <int> class F, class... A>
-void dispatch_m(int m, A&&... args) {
-  switch (m) {
-#define SADI_CASE(MM) \
-  case MM:            \
-    F<MM>::run(std::forward<A>(args)...); \
-    break;
-    SADI_FOR_EACH_M(SADI_CASE)
-#undef SADI_CASE
-    default:
-      break;
-  }
-}
-
-template <int M> int threads_per_line() { return M / sadi::Shape<M>::E; }
-template <int M> int e_of() { return sadi::Shape<M>::E; }
-template <int M> int p2_of() { return sadi::Shape<M>::P2; }
-
-struct ShapeInfo {
-  int E, P2, T;
-};
-ShapeInfo shape_of(int m) {
-  switch (m) {
-#define SADI_SH(MM) \
-  case MM:          \
-    return ShapeInfo{sadi::Shape<MM>::E, sadi::Shape<MM>::P2, MM / sadi::Shape<MM>::E};
-    SADI_FOR_EACH_M(SADI_SH)
-#undef SADI_SH
-    default:
-      return ShapeInfo{0, 0, 0};
-  }
-}
-
-sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS, c->root2M}; }
-sadi::GSTables64 gs_tables(const sadi_ctx* c) {
-  return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f};
-}
 
 template <int M> struct RowsFwd {
   static void run(const sadi_ctx* c, const double* u, double* lf_prev) {
@@ -213,24 +117,6 @@ template <int M> struct RowsGSMixed {
   }
 };
 
-sadi_status check_launch() {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
-  return SADI_OK;
-}
-
-sadi::StepScalars scalars(const sadi_ctx* c, bool first) {
-  sadi::StepScalars sc{};
-  const double t2 = c->tau * c->tau;
-  const double w = first ? 0.5 : 1.0;
-  sc.sigma = -w * t2 * c->kappa * c->h_alpha;   // h_alpha = h^-alpha
-  sc.gamma = w * t2;
-  sc.tau = c->tau;
-  sc.gkind = (int)c->g;
-  sc.gparam = c->g_param;
-  return sc;
-}
-
 // one step of the delta form on the device; mode 0: uout = 2 ucur - uprev + Uhat,
 // mode 1 (start-up): uout = ucur + Uhat with phi2.
 // Deferred update (FP64 runs): cols_mode 2 leaves Uhat in X instead of forming uout, and a
@@ -262,20 +148,6 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
   mark(4);
   if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
   return check_launch();
-}
-
-sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2) {
-  if (!domain) return fail(SADI_E_INVALID, "domain is NULL");
-  if (!finite_all({alpha, kappa, tau, domain[0], domain[1]}))
-    return fail(SADI_E_INVALID, "non-finite parameter");
-  if (!(alpha > 1.0 && (alpha < 2.0 || (allow2 && alpha <= 2.0))))
-    return fail(SADI_E_INVALID, "alpha must lie in (1, 2)");
-  if (!(kappa > 0.0)) return fail(SADI_E_INVALID, "kappa must be positive");
-  if (!(tau > 0.0)) return fail(SADI_E_INVALID, "tau must be positive");
-  if (!(domain[1] > domain[0])) return fail(SADI_E_INVALID, "domain must satisfy b > a");
-  if (n < 1) return fail(SADI_E_INVALID, "N must be >= 1");
-  if (!supported_n(n)) return fail(SADI_E_UNSUPPORTED, "N + 1 must be a power of two in [16, 4096]");
-  return SADI_OK;
 }
 
 sadi_status build_ctx(double alpha, double kappa, int n, double tau, const double* domain,
@@ -409,7 +281,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
 
 extern "C" {
 
-const char* sadi_last_error(void) { return g_last_error.c_str(); }
+const char* sadi_last_error(void) { return sadi_impl::g_last_error.c_str(); }
 
 sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const double* domain, sadi_ctx** out) {
   if (!out) return fail(SADI_E_INVALID, "out is NULL");

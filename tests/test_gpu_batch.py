@@ -1,0 +1,122 @@
+"""Batched S-ADI (instances of different N, alpha, kappa in one set of launches) against
+the CPU oracle, for both line-sweep paths, with and without HIP graph replay."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import scheme as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TAU = 5e-3
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(G):
+    return torch.from_numpy(np.ascontiguousarray(G.T)).to(_dev())
+
+
+def from_dev(t):
+    return t.detach().cpu().numpy().T.copy()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+_ref = {}
+
+
+def members():
+    return W.batch_members(7, seed=11, n_choices=(15, 31, 63, 127))
+
+
+def reference(mb, nsteps):
+    """Oracle (u^{nsteps-1}, u^nsteps) from phi1 and phi2 = 0.3 phi1-shaped field."""
+    key = (mb, nsteps)
+    if key not in _ref:
+        P = S.Problem(alpha=mb.alpha, kappa=mb.kappa, n=mb.n, tau=TAU, g="neg_sin")
+        phi1 = mb.phi1()
+        phi2 = 0.3 * W.asymmetric_field(mb.n, seed=mb.n)
+        _ref[key] = P.run(phi1, phi2, nsteps)
+    return _ref[key]
+
+
+def make_batch(path=None, graph=False):
+    from paper_2312_06206_amd import Batch
+    _dev()
+    ms = members()
+    b = Batch([m.n for m in ms], [m.alpha for m in ms], [m.kappa for m in ms], TAU, dense_max_n=127)
+    if path is not None:
+        for n in sorted({m.n for m in ms}):
+            b.set_path(n, path)
+    b.set_graph(graph)
+    u0 = [to_dev(m.phi1()) for m in ms]
+    u1 = [torch.zeros_like(t) for t in u0]
+    p2 = [to_dev(0.3 * W.asymmetric_field(m.n, seed=m.n)) for m in ms]
+    b.bind(u0, u1, p2)
+    return b, ms, u0, u1
+
+
+@pytest.mark.parametrize("path,graph", [("fft_gs", False), ("fft_gs", True), ("dense", False), ("dense", True)])
+def test_batch_run_matches_oracle(path, graph):
+    _say(f"batch path={path} graph={graph}")
+    b, ms, u0, u1 = make_batch(path, graph)
+    with b:
+        b.first_step()
+        b.run(6)                      # steps 2..7
+        for k, m in enumerate(ms):
+            ref_prev, ref_cur = reference(m, 7)
+            assert rel(from_dev(u1[k]), ref_cur) < 1e-11, (k, m)
+            assert rel(from_dev(u0[k]), ref_prev) < 1e-11, (k, m)
+
+
+@pytest.mark.parametrize("counts", [(0, 1, 2), (3, 5), (4, 4)])
+def test_batch_run_lengths_and_graph_replays(counts):
+    """Several runs in a row (graph replays with eager work and synchronisation between
+    them); every run is checked against the oracle."""
+    _say(f"batch run lengths {counts}")
+    b, ms, u0, u1 = make_batch("fft_gs", True)
+    with b:
+        b.first_step()
+        done = 1
+        for c in counts:
+            b.run(c)
+            done += c
+            torch.cuda.synchronize()
+            for k, m in enumerate(ms):
+                ref_prev, ref_cur = reference(m, done)
+                assert rel(from_dev(u1[k]), ref_cur) < 1e-11, (c, k, m)
+                assert rel(from_dev(u0[k]), ref_prev) < 1e-11, (c, k, m)
+
+
+def test_batch_tune_keeps_state():
+    _say("batch tune")
+    b, ms, u0, u1 = make_batch()
+    with b:
+        b.first_step()
+        before = [t.clone() for t in u0 + u1]
+        groups = b.tune(steps=3)
+        after = u0 + u1
+        assert all(torch.equal(x, y) for x, y in zip(before, after))
+        assert sorted(g["n"] for g in groups) == sorted({m.n for m in ms})
+        for g in groups:
+            assert g["ms_fft_gs"] > 0 and g["ms_dense"] > 0
+            assert g["path"] == ("dense" if g["ms_dense"] < g["ms_fft_gs"] else "fft_gs")
+        b.run(3)
+        for k, m in enumerate(ms):
+            assert rel(from_dev(u1[k]), reference(m, 4)[1]) < 1e-11

@@ -97,3 +97,26 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(ImportError):
         binding.load_library()
+
+
+def test_batch_create_rejects_bad_arguments_without_touching_the_gpu():
+    """Validation of the batched entry point happens before any device work."""
+    import ctypes
+    from paper_2312_06206_amd import binding as B
+    lib = B.load_library()
+    dom = np.array([-1.0, 1.0])
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int * 2)(63, 127)
+    al = np.array([1.5, 1.5])
+    ka = np.array([1.0, 1.0])
+    assert lib.sadi_batch_create(0, n, B._dptr(al), B._dptr(ka), 1e-3, B._dptr(dom), 127, ctypes.byref(h)) == -1
+    assert lib.sadi_batch_create(2, None, B._dptr(al), B._dptr(ka), 1e-3, B._dptr(dom), 127, ctypes.byref(h)) == -1
+    bad = np.array([1.5, 2.5])          # alpha outside (1, 2) for the second instance
+    assert lib.sadi_batch_create(2, n, B._dptr(bad), B._dptr(ka), 1e-3, B._dptr(dom), 127, ctypes.byref(h)) == -1
+    assert b"instance 1" in lib.sadi_last_error()
+    n_bad = (ctypes.c_int * 2)(63, 100)   # N + 1 not a power of two
+    assert lib.sadi_batch_create(2, n_bad, B._dptr(al), B._dptr(ka), 1e-3, B._dptr(dom), 127,
+                                 ctypes.byref(h)) == -4
+    assert not h.value
+    assert lib.sadi_batch_run(None, 1) == -5
+    assert lib.sadi_batch_destroy(None) == -5

@@ -116,3 +116,30 @@ CONFIG1 = Workload("config1", n=63, alpha=1.5, kappa=1.0, tau=1.0 / 64, steps=64
 def config2(n: int = 4095, alpha: float = 1.5, seed: int = 0, steps: int = 1000) -> Workload:
     assert n in (1023, 2047, 4095)
     return Workload(f"sadi_N{n}_a{alpha}", n=n, alpha=alpha, kappa=1.0, tau=1e-3, steps=steps, seed=seed)
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchMember:
+    """One problem of a batch: Omega = (-1,1)^2, g = -sin u, phi2 = 0 unless given, a
+    Gaussian bump with seeded width and centre as phi1."""
+    n: int
+    alpha: float
+    kappa: float
+    width: float
+    center: tuple
+
+    def phi1(self, domain=(-1.0, 1.0)) -> np.ndarray:
+        return gaussian_bump(self.n, domain, width=self.width, center=self.center)
+
+
+def batch_members(count: int, seed: int, n_choices=(127, 255, 511, 1023)) -> list:
+    """Seeded batch of uneven problems: N uniform over n_choices, alpha ~ U(1.1, 1.9),
+    kappa ~ U(0.5, 2), bump width ~ U(0.05, 0.3), centre ~ U(-0.3, 0.3)^2."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(n_choices))
+        out.append(BatchMember(n=n, alpha=float(rng.uniform(1.1, 1.9)), kappa=float(rng.uniform(0.5, 2.0)),
+                               width=float(rng.uniform(0.05, 0.3)),
+                               center=(float(rng.uniform(-0.3, 0.3)), float(rng.uniform(-0.3, 0.3)))))
+    return out
