@@ -153,6 +153,24 @@ sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out);
 sadi_status sadi_host_line_generator(double alpha, double kappa, int n, double tau, const double* domain,
                                      double* out);
 
+/* Reverse-mode (adjoint) step, for gradients of a scalar J(u^K) with respect to phi1 and
+ * kappa through the delta form above.  With J_n = H^-1 (-c kappa L_h + c diag g'(u^n)) H^-1
+ * the Jacobian of the increment (c = tau^2, or tau^2/2 for the start-up step; H, L_h
+ * symmetric, so J_n^T has the same form with the sweeps applied first):
+ *   mode 0 (step n >= 1):  a_cur = 2 a_next - a_next2 + J_n^T a_next,
+ *   mode 1 (start-up n=0): a_cur =   a_next - a_next2 + J_0^T a_next   (= dJ/dphi1),
+ * where a_next = dJ/du^{n+1}, a_next2 = dJ/du^{n+2} (NULL: zero), both totals.  dkappa
+ * (device pointer to one double) is incremented by <a_next, d u^{n+1} / d kappa> at fixed
+ * u^n, u^{n-1}: -c <L_h z, u^n> - (2 <a, U> - <H_x^-1 a, U> - <H_y^-1 a, U>) / kappa with
+ * z = H^-1 a H^-1 and U = u^{n+1} - u^n - (u^n - u^{n-1}) (mode 1: u^1 - u^0); the sweep terms
+ * use d H^-1 / d kappa = -H^-1 (H - I) H^-1 / kappa.  u_prev = u^{n-1} (unused for mode 1),
+ * u_cur = u^n, u_next = u^{n+1}: device grids as above; a_cur must not alias the other
+ * arguments.  float64 contexts only (SADI_E_UNSUPPORTED otherwise).  Uses the context's
+ * workspaces; asynchronous on the context stream. */
+sadi_status sadi_adjoint_step(sadi_ctx* c, int mode, const double* u_prev, const double* u_cur,
+                              const double* u_next, const double* a_next, const double* a_next2, double* a_cur,
+                              double* dkappa);
+
 /* ---------------------------------------------------------------------------------
  * Batches: many independent problems of the same scheme (same tau, domain and g = -sin u,
  * FP64), each with its own N, alpha and kappa, advanced together.  Instances with equal N

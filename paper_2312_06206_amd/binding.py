@@ -60,6 +60,7 @@ def load_library() -> ctypes.CDLL:
         "sadi_host_riesz_coeffs": (I, [D, I, DP]),
         "sadi_host_laplacian_coeffs": (I, [D, I, DP]),
         "sadi_host_line_generator": (I, [D, D, I, D, DP, DP]),
+        "sadi_adjoint_step": (I, [VP, I, VP, VP, VP, VP, VP, VP, VP]),
         "sadi_batch_create": (I, [I, P(I), DP, DP, D, DP, I, P(VP)]),
         "sadi_batch_bind": (I, [VP, P(VP), P(VP), P(VP)]),
         "sadi_batch_first_step": (I, [VP]),
@@ -218,6 +219,21 @@ class Solver:
         _check(load_library().sadi_apply_lh(self._ctx, ctypes.c_void_p(_grid_ptr(u, n)),
                                             ctypes.c_void_p(_grid_ptr(out, n))))
         return out
+
+    def adjoint_step(self, mode: int, u_prev, u_cur, u_next, a_next, a_next2, a_cur, dkappa):
+        """One reverse step (include/sadi.h, sadi_adjoint_step); a_cur written, dkappa (a
+        float64 CUDA tensor of one element) incremented."""
+        import torch
+        n = self.n
+        if not (isinstance(dkappa, torch.Tensor) and dkappa.dtype == torch.float64 and dkappa.is_cuda
+                and dkappa.numel() == 1):
+            raise TypeError("dkappa must be a one-element float64 CUDA tensor")
+        ptr = lambda t: ctypes.c_void_p(None if t is None else _grid_ptr(t, n))
+        self._bind_stream()
+        _check(load_library().sadi_adjoint_step(self._ctx, int(mode), ptr(u_prev), ptr(u_cur), ptr(u_next),
+                                                ptr(a_next), ptr(a_next2), ptr(a_cur),
+                                                ctypes.c_void_p(dkappa.data_ptr())))
+        return a_cur
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -62,6 +62,7 @@ struct sadi_ctx {
   float* f32 = nullptr;
   double* sig_e = nullptr;
   double* sig_o = nullptr;
+  double* partial = nullptr;   // 4 N partial sums (adjoint inner products)
 
   std::vector<void*> allocs;
 

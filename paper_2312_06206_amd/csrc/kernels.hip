@@ -774,6 +774,106 @@ leapfrog_batched(const BatchInst* __restrict__ bi, int mode, int ic, int ip, int
   }
 }
 
+
+// ----------------------------------------------------------------------------------
+// adjoint of a step: inner products and the combination (one workgroup per grid row,
+// partial sums per row reduced in a fixed order, so results are deterministic)
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* out) {
+  __shared__ double red[NV][256];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = red[k][0];
+  }
+}
+
+// row j: sums of a Uhat, p Uhat, q Uhat with Uhat = unext - 2 ucur + uprev (mode 0) or
+// unext - ucur (mode 1); a, ucur, unext, uprev pitch n, p and q pitch ldx
+__global__ void __launch_bounds__(256)
+adjoint_dots_kernel(int mode, const double* __restrict__ a, const double* __restrict__ p, const double* __restrict__ q,
+                    int ldx, const double* __restrict__ uprev, const double* __restrict__ ucur,
+                    const double* __restrict__ unext, int n, double* __restrict__ partial) {
+  const int j = blockIdx.x;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const size_t o = (size_t)j * n + i, ox = (size_t)j * ldx + i;
+    const double uh = mode == 0 ? unext[o] - 2.0 * ucur[o] + uprev[o] : unext[o] - ucur[o];
+    v[0] += a[o] * uh;
+    v[1] += p[ox] * uh;
+    v[2] += q[ox] * uh;
+  }
+  block_sums<3>(v, partial + 4 * (size_t)j);
+}
+
+// acur = ca anext - anext2 + c2 (-kappa Lz + g'(ucur) z), with Lz read from acur (same
+// element, read before write); partial[4 j + 3] = sum over row j of Lz ucur
+__global__ void __launch_bounds__(256)
+adjoint_combine_kernel(double ca, double c2, double kappa, int gkind, double gparam,
+                       const double* __restrict__ anext, const double* __restrict__ anext2,
+                       const double* __restrict__ z, int ldx, const double* __restrict__ ucur, double* acur, int n,
+                       double* __restrict__ partial) {
+  const int j = blockIdx.x;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const size_t o = (size_t)j * n + i;
+    const double lz = acur[o], zz = z[(size_t)j * ldx + i], u = ucur[o];
+    double gp;
+    switch (gkind) {
+      case 1: gp = -cos(u); break;
+      case 2: gp = -3.0 * u * u; break;
+      case 3: gp = -gparam; break;
+      default: gp = 0.0; break;
+    }
+    v[0] += lz * u;
+    const double prev2 = anext2 ? anext2[o] : 0.0;
+    acur[o] = ca * anext[o] - prev2 + c2 * (gp * zz - kappa * lz);
+  }
+  block_sums<1>(v, partial + 4 * (size_t)j + 3);
+}
+
+// dkappa += -c2 sum(Lz u) - (2 sum(a Uhat) - sum(p Uhat) - sum(q Uhat)) / kappa
+__global__ void __launch_bounds__(256)
+adjoint_finish_kernel(const double* __restrict__ partial, int nrows, double c2, double kappa,
+                      double* __restrict__ dkappa) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = threadIdx.x; r < nrows; r += 256) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += partial[4 * (size_t)r + k];
+  }
+  __shared__ double tot[4];
+  block_sums<4>(v, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) dkappa[0] += -c2 * tot[3] - (2.0 * tot[0] - tot[1] - tot[2]) / kappa;
+}
+
+void launch_adjoint_dots(int mode, const double* a, const double* p, const double* q, int ldx, const double* uprev,
+                         const double* ucur, const double* unext, int n, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_dots_kernel, dim3(n), dim3(256), 0, st, mode, a, p, q, ldx, uprev, ucur, unext, n,
+                     partial);
+}
+
+void launch_adjoint_combine(double ca, double c2, double kappa, int gkind, double gparam, const double* anext,
+                            const double* anext2, const double* z, int ldx, const double* ucur, double* acur, int n,
+                            double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_combine_kernel, dim3(n), dim3(256), 0, st, ca, c2, kappa, gkind, gparam, anext, anext2,
+                     z, ldx, ucur, acur, n, partial);
+}
+
+void launch_adjoint_finish(const double* partial, int nrows, double c2, double kappa, double* dkappa,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, st, partial, nrows, c2, kappa, dkappa);
+}
+
 // ----------------------------------------------------------------------------------
 // host-side launchers
 template <int M>

@@ -194,6 +194,15 @@ void launch_batch_cols_gs(const BatchInst* bi, int count, int ldx, int n, const 
                           hipStream_t st);
 void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int ip, int ldx, int n, hipStream_t st);
 
+// adjoint of a step (per-row partial sums in partial[4 j + k], then one finishing block)
+void launch_adjoint_dots(int mode, const double* a, const double* p, const double* q, int ldx, const double* uprev,
+                         const double* ucur, const double* unext, int n, double* partial, hipStream_t st);
+void launch_adjoint_combine(double ca, double c2, double kappa, int gkind, double gparam, const double* anext,
+                            const double* anext2, const double* z, int ldx, const double* ucur, double* acur, int n,
+                            double* partial, hipStream_t st);
+void launch_adjoint_finish(const double* partial, int nrows, double c2, double kappa, double* dkappa,
+                           hipStream_t st);
+
 template <int M>
 void launch_rows_rhs_mixed(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2,
                            double* X, int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab,

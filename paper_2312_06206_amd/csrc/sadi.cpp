@@ -84,6 +84,17 @@ template <int M> struct ColsGS {
     sadi::launch_cols_gs<M>(mode, c->X, c->ldX, ucur, uprev, uout, c->n, c->n, tables(c), gs_tables(c), c->stream);
   }
 };
+template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ldX buffer
+  static void run(const sadi_ctx* c, double* buf) {
+    sadi::launch_cols_gs<M>(2, buf, c->ldX, nullptr, nullptr, nullptr, c->n, c->n, tables(c), gs_tables(c),
+                            c->stream);
+  }
+};
+template <int M> struct RowsFwdPitched {  // spectrum of a grid function with row pitch ld
+  static void run(const sadi_ctx* c, const double* u, int ld) {
+    sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, ld, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
+  }
+};
 template <int M> struct RowsGS {
   static void run(const sadi_ctx* c, double* lines, int ld, int nlines) {
     sadi::launch_rows_gs<M>(lines, ld, nlines, c->n, tables(c), gs_tables(c), c->stream);
@@ -252,6 +263,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->f32, sizeof(float) * n)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->sig_e, sizeof(double) * m)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->sig_o, sizeof(double) * m)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->partial, sizeof(double) * 4 * (size_t)n)) != SADI_OK) return bail(st);
 
   auto up = [&](void* dst, const void* src, size_t bytes) -> sadi_status {
     hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -405,6 +417,41 @@ sadi_status sadi_apply_lh(sadi_ctx* c, const double* u, double* out) {
   sadi::StepScalars sc{};
   sc.sigma = c->h_alpha;
   dispatch_m<RowsRhs>(c->m, c, 2, u, (const double*)nullptr, out, c->n, sc);
+  return check_launch();
+}
+
+sadi_status sadi_adjoint_step(sadi_ctx* c, int mode, const double* u_prev, const double* u_cur,
+                              const double* u_next, const double* a_next, const double* a_next2, double* a_cur,
+                              double* dkappa) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (mode != 0 && mode != 1) return fail(SADI_E_INVALID, "mode must be 0 (n >= 1) or 1 (start-up step)");
+  if (!u_cur || !u_next || !a_next || !a_cur || !dkappa || (mode == 0 && !u_prev))
+    return fail(SADI_E_INVALID, "NULL array");
+  if (a_cur == a_next || a_cur == a_next2 || a_cur == u_cur)
+    return fail(SADI_E_INVALID, "a_cur must not alias a_next, a_next2 or u_cur");
+  if (c->prec != SADI_FP64) return fail(SADI_E_UNSUPPORTED, "the adjoint runs in float64 only");
+  const int n = c->n;
+  const size_t w = sizeof(double) * n;
+  // Q = the first N x ldX doubles of the spectrum buffer, P = X
+  double* P = c->X;
+  double* Q = reinterpret_cast<double*>(c->S);
+  SADI_HIP(hipMemcpy2DAsync(P, sizeof(double) * c->ldX, a_next, w, w, n, hipMemcpyDeviceToDevice, c->stream));
+  SADI_HIP(hipMemcpy2DAsync(Q, sizeof(double) * c->ldX, a_next, w, w, n, hipMemcpyDeviceToDevice, c->stream));
+  dispatch_m<RowsGS>(c->m, c, P, c->ldX, n);                      // p = H_x^-1 a
+  dispatch_m<ColsGSPitched>(c->m, c, Q);                          // q = H_y^-1 a
+  sadi::launch_adjoint_dots(mode, a_next, P, Q, c->ldX, u_prev, u_cur, u_next, n, c->partial, c->stream);
+  dispatch_m<ColsGSPitched>(c->m, c, P);                          // z = H_y^-1 H_x^-1 a
+  dispatch_m<RowsFwdPitched>(c->m, c, P, c->ldX);                 // L_h z into a_cur
+  dispatch_m<ColsConv>(c->m, c);
+  sadi::StepScalars sc{};
+  sc.sigma = c->h_alpha;
+  dispatch_m<RowsRhs>(c->m, c, 2, (const double*)P, (const double*)nullptr, a_cur, n, sc);
+  const double t2 = c->tau * c->tau;
+  const double c2 = mode == 0 ? t2 : 0.5 * t2;
+  const double ca = mode == 0 ? 2.0 : 1.0;
+  sadi::launch_adjoint_combine(ca, c2, c->kappa, (int)c->g, c->g_param, a_next, a_next2, P, c->ldX, u_cur, a_cur, n,
+                               c->partial, c->stream);
+  sadi::launch_adjoint_finish(c->partial, n, c2, c->kappa, dkappa, c->stream);
   return check_launch();
 }
 
