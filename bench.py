@@ -139,6 +139,42 @@ def batched_leg(seed: int, count: int, steps: int, unbatched_sample: int) -> dic
             "one_by_one_sample_steps": unbatched_sample}
 
 
+def adjoint_leg(seed: int) -> dict:
+    """Gradient of J = ||u(T) - u_obs||^2 with respect to phi1 and kappa: N = 511,
+    alpha = 1.6, 500 steps, tau = 1e-3, u_obs from kappa = 1.3 and a seeded bump, the
+    gradient at kappa = 1 and another seeded bump; checkpoints every 50 steps."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2312_06206_amd import Solver
+    from paper_2312_06206_amd.adjoint import sadi_loop
+
+    dev = torch.device("cuda:0")
+    n, alpha, tau, steps = 511, 1.6, 1e-3, 500
+    to_dev = lambda G: torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+    with Solver(alpha, 1.3, n, tau) as s:
+        a = to_dev(W.seeded_bump(n, seed))
+        u_obs = s.first_step(a, torch.zeros_like(a))
+        s.run(a, u_obs, steps - 1)
+    x = to_dev(W.seeded_bump(n, seed + 1)).requires_grad_(True)
+    k = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uK = sadi_loop(x, k, alpha, n, tau, steps, checkpoint=50)
+    J = ((uK - u_obs) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": "N=511, alpha=1.6, 500 steps, tau=1e-3, loss ||u(T)-u_obs||^2, u_obs from kappa=1.3, "
+                        "gradient w.r.t. kappa and phi1 at kappa=1, checkpoint every 50 steps",
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "loss": float(J.item()), "dJ_dkappa": float(k.grad.item()),
+            "grad_phi1_norm": float(x.grad.norm().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +187,7 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 / FP32+refine runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (uneven N) leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) leg")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -265,6 +302,8 @@ def main():
     s.close()
     if not args.no_batched:
         out["batched"] = batched_leg(args.seed, args.batch_count, args.batch_steps, 20)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
