@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "context.hpp"
@@ -248,13 +249,32 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
   };
   b->count = count;
   b->ctx.assign(count, nullptr);
-  for (int i = 0; i < count; ++i) {
-    sadi_status st = sadi_setup(alpha[i], kappa[i], n[i], tau, domain, &b->ctx[i]);
-    if (st != SADI_OK) {
-      const std::string msg = std::string("instance ") + std::to_string(i) + ": " + sadi_last_error();
-      destroy_batch(b);
-      return fail(st, msg);
-    }
+  {
+    // instances set up concurrently, one host thread each
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int workers = (int)std::min<unsigned>(std::min<unsigned>(hw, 16u), (unsigned)count);
+    const int inner = 1;
+    std::vector<sadi_status> status(count, SADI_OK);
+    std::vector<std::string> errors(count);
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = 0;
+    std::vector<std::thread> pool;
+    for (int w = 0; w < workers; ++w)
+      pool.emplace_back([&, w] {
+        (void)hipSetDevice(device);   // the caller's device, as for sadi_setup
+        g_setup_threads = inner;
+        for (int i = w; i < count; i += workers) {
+          status[i] = sadi_setup(alpha[i], kappa[i], n[i], tau, domain, &b->ctx[i]);
+          if (status[i] != SADI_OK) errors[i] = sadi_last_error();
+        }
+      });
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < count; ++i)
+      if (status[i] != SADI_OK) {
+        const std::string msg = std::string("instance ") + std::to_string(i) + ": " + errors[i];
+        destroy_batch(b);
+        return fail(status[i], msg);
+      }
   }
   if (hipStreamCreate(&b->own_stream) != hipSuccess) {
     b->own_stream = nullptr;

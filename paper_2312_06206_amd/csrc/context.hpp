@@ -18,6 +18,8 @@ sadi_status fail(sadi_status st, const std::string& msg);
 sadi_status check_launch();
 bool finite_all(std::initializer_list<double> v);
 bool supported_n(int n);
+// host threads for the set-up maths of the calling thread (0: all hardware threads)
+extern thread_local int g_setup_threads;
 // argument checks of sadi_setup (allow2: alpha = 2 accepted, for injected tables)
 sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2);
 }  // namespace sadi_impl

@@ -18,6 +18,7 @@
 namespace sadi_impl {
 
 thread_local std::string g_last_error;
+thread_local int g_setup_threads = 0;
 
 sadi_status fail(sadi_status st, const std::string& msg) {
   g_last_error = msg;
@@ -211,7 +212,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   }
   c->ldlam = m + 1 + ((8 - (m + 1) % 8) % 8);
   std::vector<double> hlam((size_t)(m + 1) * c->ldlam, 0.0);
-  sadi::bccb_eigenvalues(a2, n, hlam.data(), c->ldlam);
+  sadi::bccb_eigenvalues(a2, n, hlam.data(), c->ldlam, g_setup_threads);
 
   // ---- mixed precision tables
   std::vector<float2> hrootM32(sh.T), hrootS32(sh.E), hq32(m), hls32(m), hlc32(m);
@@ -302,7 +303,7 @@ sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const doub
   if (st != SADI_OK) return st;
   try {
     const std::vector<double> a1 = sadi::riesz_coeffs(alpha, n + 1);
-    const std::vector<double> a2 = sadi::laplacian_coeffs(alpha, n);
+    const std::vector<double> a2 = sadi::laplacian_coeffs(alpha, n, g_setup_threads);
     return build_ctx(alpha, kappa, n, tau, domain, a1, a2, out);
   } catch (const std::bad_alloc&) {
     return fail(SADI_E_NOMEM, "host allocation failed in setup");
