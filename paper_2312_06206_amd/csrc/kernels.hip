@@ -429,6 +429,41 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
 //
 // rhs_phase: everything before the line solve.  Returns false for MODE 2 (output written);
 // otherwise d[m] = (B[k], B[M-1-k]) with B[N] = 0.
+// B[k] += gamma g(u[k]) (+ tau phi2[k] for the start-up step) for this thread's k < N, in
+// place in LDS; returns whether some sine argument lies beyond the fast reduction's range
+template <int MODE, int GK, class L_t>
+__device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const double* __restrict__ urow,
+                                              const double* __restrict__ prow, const StepScalars& sc) {
+  constexpr int E = L_t::E, T = L_t::T;
+  const int t = L.t;
+  bool far = false;
+#pragma unroll
+  for (int m = 0; m < E / 2; ++m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool last = (h == 1 && m == E / 2 - 1);
+      if (last && t == T - 1) continue;       // B[N] = 0
+      const int lane_off = 2 * t + h;
+      const double uv = (urow + 2 * T * m)[lane_off];
+      double gv = 0.0;
+      if constexpr (GK == 1) {
+        far |= !(fabs(uv) <= kSinFastMax);
+        gv = -sin_fp64(uv);
+      } else if constexpr (GK == 2) {
+        gv = -uv * uv * uv;
+      } else if constexpr (GK == 3) {
+        gv = -sc.gparam * uv;
+      }
+      double b = sc.gamma * gv;
+      if constexpr (MODE == 1) b += sc.tau * (prow + 2 * T * m)[lane_off];
+      const int k = 2 * (t + T * m) + h;
+      L.put_real(buf, k, L.get_real(buf, k) + b);
+    }
+    if (m % 2 == 1) asm volatile("" ::: "memory");   // bound the live sine temporaries
+  }
+  return far;
+}
+
 template <int MODE, class L_t>
 __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const V* __restrict__ srow,
                                           const double* __restrict__ urow, const double* __restrict__ prow,
@@ -478,22 +513,13 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
         L.put_real(buf, 2 * (t + T * m) + h, (last && t == T - 1) ? 0.0 : sc.sigma * xv);
       }
     }
+    // one loop per kind of g (the kind is uniform: no per-element branches)
     bool far = false;   // some sin argument beyond the fast reduction's range
-#pragma unroll
-    for (int m = 0; m < E / 2; ++m) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const bool last = (h == 1 && m == E / 2 - 1);
-        if (last && t == T - 1) continue;       // B[N] = 0
-        const int lane_off = 2 * t + h;
-        const double uv = (urow + 2 * T * m)[lane_off];
-        far |= !(fabs(uv) <= kSinFastMax);
-        double b = sc.gamma * g_of(uv, sc.gkind, sc.gparam);
-        if constexpr (MODE == 1) b += sc.tau * (prow + 2 * T * m)[lane_off];
-        const int k = 2 * (t + T * m) + h;
-        L.put_real(buf, k, L.get_real(buf, k) + b);
-      }
-      if (m % 2 == 1) asm volatile("" ::: "memory");   // bound the live sine temporaries
+    switch (sc.gkind) {
+      case 1: far = add_pointwise<MODE, 1>(L, buf, urow, prow, sc); break;
+      case 2: add_pointwise<MODE, 2>(L, buf, urow, prow, sc); break;
+      case 3: add_pointwise<MODE, 3>(L, buf, urow, prow, sc); break;
+      default: add_pointwise<MODE, 0>(L, buf, urow, prow, sc); break;
     }
     if (sc.gkind == 1 && far) {
       // rare: replace the fast sine by the library's for the far arguments of this lane
