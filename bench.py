@@ -175,6 +175,59 @@ def adjoint_leg(seed: int) -> dict:
             "grad_phi1_norm": float(x.grad.norm().item())}
 
 
+# the paper's own CPU timings (seconds, S-ADI column) and printed errors for two of its
+# workloads: Table 1 (sine-Gordon, h = 1/40, N = 799) and Table 3 (Klein-Gordon, h = 1/50,
+# N = 999), alpha = 1.5, Omega = (-10, 10)^2
+PAPER_ROWS = [
+    {"table": "Table 1", "g": "neg_sin", "n": 799, "T": 5.0, "tau": 1.0 / 80, "paper_cpu_s": 223.1865,
+     "paper_error1": 1.4136e-4},
+    {"table": "Table 3", "g": "neg_cube", "n": 999, "T": 8.0, "tau": 1.0 / 50, "paper_cpu_s": 430.4121,
+     "paper_error1": 6.7184e-3},
+]
+
+
+def paper_leg() -> list:
+    """Two of the paper's own experiments run as printed (kappa = 1): the GPU time of the
+    run the paper timed, and Error_1 against the run with tau/2."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2312_06206_amd import Solver
+
+    dev = torch.device("cuda:0")
+    out = []
+    for row in PAPER_ROWS:
+        n, alpha = row["n"], 1.5
+        data = W.sine_gordon_data if row["g"] == "neg_sin" else W.klein_gordon_data
+        phi1, phi2 = data(n)
+        finals, secs = {}, {}
+        for tau in (row["tau"], row["tau"] / 2):
+            steps = round(row["T"] / tau)
+            with Solver(alpha, 1.0, n, tau, (-10.0, 10.0), g=row["g"]) as s:
+                a = torch.from_numpy(np.ascontiguousarray(phi1.T)).to(dev)
+                p2 = torch.from_numpy(np.ascontiguousarray(phi2.T)).to(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b = s.first_step(a, p2)
+                s.run(a, b, steps - 1)
+                torch.cuda.synchronize()
+                secs[tau] = time.perf_counter() - t0
+                finals[tau] = b.cpu().numpy()
+        h = 20.0 / (n + 1)
+        err = math.sqrt(h * h * float(np.sum((finals[row["tau"]] - finals[row["tau"] / 2]) ** 2)))
+        steps = round(row["T"] / row["tau"])
+        out.append({"workload": f"{row['table']}: g={row['g']}, alpha=1.5, N={n}, tau={row['tau']:.6g}, "
+                                f"{steps} steps, Omega=(-10,10)^2",
+                    "gpu_s": secs[row["tau"]], "paper_cpu_s": row["paper_cpu_s"],
+                    "ratio_paper_over_gpu": row["paper_cpu_s"] / secs[row["tau"]],
+                    "error1": err, "paper_error1": row["paper_error1"],
+                    "note": "the paper names no hardware for its timings: context only"})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +241,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 / FP32+refine runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (uneven N) leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) leg")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's own workloads")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -304,6 +358,8 @@ def main():
         out["batched"] = batched_leg(args.seed, args.batch_count, args.batch_steps, 20)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.seed)
+    if not args.no_paper:
+        out["paper_workloads"] = paper_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)

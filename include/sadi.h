@@ -28,7 +28,12 @@
  * thread-safe; any number of contexts may coexist.  The library never aborts:
  * every failure is a status plus a message from sadi_last_error().
  *
- * Supported sizes: N + 1 a power of two with 16 <= N + 1 <= 4096.
+ * Supported sizes: 15 <= N <= 4095.  The line transforms have length M, the smallest power
+ * of two >= N + 1 (the block-circulant embedding of L_h has size 2M).  The line solves
+ * apply the Gohberg-Semencul formula to H_M = I + beta T(a_0..a_{M-1}) and correct to
+ * H_N^-1 through the Schur complement, H_N^-1 v = w[0:N] - F w[N:M] with w = H_M^-1 [v; 0]
+ * and F = -H_N^-1 H_M[0:N, N:M]: a rank-one correction when N + 1 = M (the fast case),
+ * rank M - N otherwise.  The float32 line solves need N + 1 = M.
  */
 #ifndef SADI_H
 #define SADI_H
@@ -44,7 +49,7 @@ typedef enum {
   SADI_E_INVALID = -1,     /* bad argument (range, NULL, size) */
   SADI_E_NOMEM = -2,       /* device or host allocation failed */
   SADI_E_DEVICE = -3,      /* HIP runtime error (launch, copy, earlier async fault) */
-  SADI_E_UNSUPPORTED = -4, /* valid problem this build does not handle (e.g. N+1 not a power of two) */
+  SADI_E_UNSUPPORTED = -4, /* valid problem this build does not handle (N outside [15, 4095], ...) */
   SADI_E_STATE = -5        /* NULL or destroyed context */
 } sadi_status;
 
@@ -68,7 +73,7 @@ typedef enum {
  * Validates 1 < alpha < 2, kappa > 0, tau > 0, domain[1] > domain[0] (all finite).
  * Computes on the host: the 1D coefficients a_k (closed form, section 2), the 2D
  * coefficients a_ij of L_h (Fourier coefficients of the symbol), the generating
- * vector H^-1 e_1 of the bordered line matrix and its circulant / skew-circulant
+ * vector H_M^-1 e_1 of the size-M line matrix and its circulant / skew-circulant
  * eigenvalues (Proposition 1), and the eigenvalues of the block-circulant
  * embedding of L_h; uploads them and allocates the device workspaces.  Uses the
  * current HIP device.  Host-synchronous.  Defaults: g = -sin u, float64.

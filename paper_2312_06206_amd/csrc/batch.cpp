@@ -199,6 +199,7 @@ sadi_status upload_desc(sadi_batch* b, Group& g, bool scratch, const std::vector
     d.lam_s = c->lam_s;
     d.lam_c = c->lam_c;
     d.f = c->f;
+    d.r = c->r;
     d.sc = scalars(c, false);
   }
   sadi::BatchInst* dst = scratch ? g.d_scratch_inst : g.d_inst;
@@ -296,7 +297,7 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
       by_n[n[i]] = (int)b->groups.size();
       Group g;
       g.n = n[i];
-      g.m = n[i] + 1;
+      g.m = b->ctx[i]->m;
       b->groups.push_back(g);
       b->groups.back().members.push_back(i);
     } else {

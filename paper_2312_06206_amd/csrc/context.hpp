@@ -33,6 +33,7 @@ sadi_status validate_problem(double alpha, double kappa, int n, double tau, cons
 
 struct sadi_ctx {
   int n = 0, m = 0;
+  int r = 1;                   // M - N: rank of the correction from H_M^-1 to H_N^-1
   double alpha = 0, kappa = 0, tau = 0, a = 0, b = 0, h = 0, h_alpha = 0, beta = 0;
   sadi_g_kind g = SADI_G_NEG_SIN;
   double g_param = 0.0;
@@ -144,7 +145,7 @@ inline ShapeInfo shape_of(int m) {
 
 inline sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS, c->root2M}; }
 inline sadi::GSTables64 gs_tables(const sadi_ctx* c) {
-  return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f};
+  return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f, c->r};
 }
 
 

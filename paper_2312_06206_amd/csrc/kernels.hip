@@ -42,43 +42,42 @@ __device__ __forceinline__ int xcd_group(int nblocks_used) {
 }
 
 // ----------------------------------------------------------------------------------
-// Line access in canonical layout for lines of length N = M - 1 (stride `st` elements):
-// slot m holds index k = t + T m; k = N (t = T-1, m = E-1) is the only index outside a
-// line, and M-1-k = N only for t = 0, m = 0.
-// d[m] = (v[k], v[M-1-k]) with v[N] = 0: the Gohberg-Semencul input v + i J v.
+// Line access in canonical layout for lines of n < M values (stride `st` elements): slot m
+// holds index k = t + T m; indices k >= n lie outside the line and read as zero.  Loads
+// use the clamped index min(k, n-1), so every address stays inside the line.
+// d[m] = (v[k], v[M-1-k]) with v[k] = 0 for k >= n: the Gohberg-Semencul input v + i J v.
 template <int M, int E, int T>
-__device__ __forceinline__ void load_line_pair(V* d, const double* __restrict__ v, int st, int t) {
-  // k = t + T m < N except m = E-1, t = T-1; M-1-k = (T-1-t) + T (E-1-m) < N except m = 0, t = 0
-  const int kf = t * st, kr = (T - 1 - t) * st;
+__device__ __forceinline__ void load_line_pair(V* d, const double* __restrict__ v, int st, int t, int n) {
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    d[m].x = (m == E - 1) ? (v + T * m * st)[min(t, T - 2) * st] : (v + T * m * st)[kf];
-    d[m].y = (m == 0) ? (v + T * (E - 1) * st)[min(T - 1 - t, T - 2) * st] : (v + T * (E - 1 - m) * st)[kr];
-  }
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    if (m == E - 1 && t == T - 1) d[m].x = 0.0;
-    if (m == 0 && t == 0) d[m].y = 0.0;
+    const int k = t + T * m, kr = (T - 1 - t) + T * (E - 1 - m);
+    const double xf = (v + T * m * st)[(min(k, n - 1) - T * m) * st];
+    const double xr = (v + T * (E - 1 - m) * st)[(min(kr, n - 1) - T * (E - 1 - m)) * st];
+    d[m].x = k < n ? xf : 0.0;
+    d[m].y = kr < n ? xr : 0.0;
   }
 }
 
 template <int M, int E, int T>
-__device__ __forceinline__ void store_line(const V* d, double* __restrict__ v, int st, int t) {
+__device__ __forceinline__ void store_line(const V* d, double* __restrict__ v, int st, int t, int n) {
 #pragma unroll
   for (int m = 0; m < E; ++m)
-    if (m < E - 1 || t < T - 1) (v + T * m * st)[t * st] = d[m].x;
+    if (t + T * m < n) (v + T * m * st)[t * st] = d[m].x;
 }
 
 // Same pairs for a strided line (a grid column): each element is loaded once, the reversed
 // copy comes through LDS.
 template <int M, int E, int T, class L_t>
 __device__ __forceinline__ void load_column_pair(const L_t& L, V* d, const double* __restrict__ v, int st,
-                                                 void* lds) {
+                                                 void* lds, int n) {
   const int t = L.t;
   double a[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) a[m] = (m == E - 1) ? (v + T * m * st)[min(t, T - 2) * st] : (v + T * m * st)[t * st];
-  if (t == T - 1) a[E - 1] = 0.0;
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const double x = (v + T * m * st)[(min(k, n - 1) - T * m) * st];
+    a[m] = k < n ? x : 0.0;
+  }
   double* buf = reinterpret_cast<double*>(lds);
 #pragma unroll
   for (int m = 0; m < E; ++m) L.put_real(buf, t + T * m, a[m]);
@@ -132,7 +131,7 @@ __device__ __forceinline__ void pointwise_real(VV* d, const R* __restrict__ tab,
 template <class LineT>
 __device__ __forceinline__ void gs_solve(const LineT& L, V2<typename LineT::Real>* d, void* lds,
                                          const FFTTables<typename LineT::Real>& tab,
-                                         const GSTables<typename LineT::Real>& gs) {
+                                         const GSTables<typename LineT::Real>& gs, int n) {
   using R = typename LineT::Real;
   constexpr int M = LineT::M, E = LineT::E, T = LineT::T;
   const int t = L.t;
@@ -144,12 +143,36 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V2<typename LineT::Real
   L.template transform<-1, +1>(d, lds, tab);
   pointwise<E, T, false>(d, gs.lam_c, t);
   L.template transform<+1>(d, lds, tab);
-  // w = Re(v3) + J Im(v3); bordering correction w[:N] - f * w[N]
+  // w = Re(v3) + J Im(v3); correction to H_N^-1: w[:N] - F w[N:M]
   R* buf = reinterpret_cast<R*>(lds);
   constexpr int SC = LineT::LINE_FAST_ ? LineT::LPW_ : 1;
   const int wb = L.lds_index(t), rb = L.lds_index(T - 1 - t);
 #pragma unroll
   for (int m = 0; m < E; ++m) buf[wb + SC * T * m] = d[m].y;
+  if (gs.r != 1) {
+    // N < M - 1: w for every slot, then w[N..M-1] through LDS, then the rank-r correction
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) d[m].x += buf[rb + SC * T * (E - 1 - m)];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      if (t + T * m >= n) buf[wb + SC * T * m] = d[m].x;
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < gs.r; ++j) {
+      const R wj = L.get_real(buf, n + j);
+      const R* Fj = gs.f + (size_t)j * n;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = t + T * m;
+        const R fk = (Fj + T * m)[min(k, n - 1) - T * m];
+        if (k < n) d[m].x -= fk * wj;
+      }
+    }
+    __syncthreads();
+    return;
+  }
   if (t == T - 1) L.put_real(buf, M, d[E - 1].x);   // Re v3[M-1]
   __syncthreads();
   const R wN = L.get_real(buf, M) + L.get_real(buf, 0);
@@ -213,7 +236,7 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
   float2 df[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) df[m] = float2{(float)dv[m].x, (float)dv[m].y};
-  gs_solve(Lf, df, lds, mx.tab32, mx.gs32);
+  gs_solve(Lf, df, lds, mx.tab32, mx.gs32, M - 1);
   if (!mx.refine) {
 #pragma unroll
     for (int m = 0; m < E; ++m) dv[m].x = (double)df[m].x;
@@ -240,7 +263,7 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
   for (int m = 0; m < E; ++m)
     df[m] = float2{(float)r[m], (float)L.get_real(buf, (T - 1 - t) + T * (E - 1 - m))};
   __syncthreads();
-  gs_solve(Lf, df, lds, mx.tab32, mx.gs32);
+  gs_solve(Lf, df, lds, mx.tab32, mx.gs32, M - 1);
 #pragma unroll
   for (int m = 0; m < E; ++m) dv[m].x = (double)x0[m] + (double)df[m].x;
   (void)M;
@@ -265,25 +288,26 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
   const double* hrow = LF ? hat + (size_t)yy * ldx : nullptr;
   const int t = L.t;
   V d[E];
-  // z[m] = x[2m] + i x[2m+1], x[n] = 0 for n >= N = M - 1: slots c >= E/2 are zero and
-  // only x[M-1] (odd part of the last nonzero z) falls outside the row
+  // z[j] = x[2j] + i x[2j+1], j = t + T c, x[i] = 0 for i >= N (N <= M - 1): slots c >= E/2
+  // are zero; loads use the clamped index min(i, N-1)
 #pragma unroll
   for (int c = 0; c < E; ++c) {
     if (c < E / 2) {
-      const bool edge = (c == E / 2 - 1 && t == T - 1);
-      const int ie = 2 * t, io = edge ? 2 * T - 2 : 2 * t + 1;   // offsets from 2 T c
-      double xe = (row + 2 * T * c)[ie];
-      double xo = (row + 2 * T * c)[io];
+      const int i0 = 2 * (t + T * c), base = 2 * T * c;
+      const bool ve = i0 < n, vo = i0 + 1 < n;
+      const int ie = min(i0, n - 1) - base, io = min(i0 + 1, n - 1) - base;   // offsets from 2 T c
+      double xe = (row + base)[ie];
+      double xo = (row + base)[io];
       if constexpr (LF == 1) {
-        xe = 2.0 * xe - (prow + 2 * T * c)[ie] + (hrow + 2 * T * c)[ie];
-        xo = 2.0 * xo - (prow + 2 * T * c)[io] + (hrow + 2 * T * c)[io];
+        xe = 2.0 * xe - (prow + base)[ie] + (hrow + base)[ie];
+        xo = 2.0 * xo - (prow + base)[io] + (hrow + base)[io];
         if (live) {
-          (prow + 2 * T * c)[ie] = xe;
-          if (!edge) (prow + 2 * T * c)[io] = xo;
+          if (ve) (prow + base)[ie] = xe;
+          if (vo) (prow + base)[io] = xo;
         }
       }
-      d[c].x = xe;
-      d[c].y = edge ? 0.0 : xo;
+      d[c].x = ve ? xe : 0.0;
+      d[c].y = vo ? xo : 0.0;
     } else {
       d[c] = V{0.0, 0.0};
     }
@@ -371,11 +395,12 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
   const int t = L.t;
   // Addresses: uniform base (per slot) + one per-lane offset.
   // y = N (m = E-1, t = T-1) is the zero padding row; odd lines take W_P^y c[y]
-  const int so = t * lds_ + colc;
 #pragma unroll
-  for (int m = 0; m < E; ++m)
-    d[m] = (m == E - 1) ? (S + T * m * lds_)[min(t, T - 2) * lds_ + colc] : (S + T * m * lds_)[so];
-  if (t == T - 1) d[E - 1] = V{0.0, 0.0};
+  for (int m = 0; m < E; ++m) {
+    const int y = t + T * m;   // rows y >= N are the zero padding (clamped, unused load)
+    const V v = (S + T * m * lds_)[(min(y, n - 1) - T * m) * lds_ + colc];
+    d[m] = y < n ? v : V{0.0, 0.0};
+  }
   // odd lines: W_P^y = e^{-i pi y/M} on the input, y = t + T m: the per-slot part
   // e^{-i pi m/E} here, the per-thread part e^{-i pi t/M} on the first twiddle
   shift_odd_slots(d, odd, std::make_integer_sequence<int, E>{});
@@ -417,7 +442,7 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
     const int wo = t * lds_ + col;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if (m < E - 1 || t < T - 1) (S + T * m * lds_)[wo] = cadd(d[m], (xb + T * CPW * m)[xo]);
+      if (t + T * m < n) (S + T * m * lds_)[wo] = cadd(d[m], (xb + T * CPW * m)[xo]);
     }
   }
 }
@@ -428,12 +453,12 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
 // 1 = start-up step (n = 0, adds tau phi2), 2 = L_h only (X = sigma x, no solve).
 //
 // rhs_phase: everything before the line solve.  Returns false for MODE 2 (output written);
-// otherwise d[m] = (B[k], B[M-1-k]) with B[N] = 0.
+// otherwise d[m] = (B[k], B[M-1-k]) with B[k] = 0 for k >= N.
 // B[k] += gamma g(u[k]) (+ tau phi2[k] for the start-up step) for this thread's k < N, in
 // place in LDS; returns whether some sine argument lies beyond the fast reduction's range
 template <int MODE, int GK, class L_t>
 __device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const double* __restrict__ urow,
-                                              const double* __restrict__ prow, const StepScalars& sc) {
+                                              const double* __restrict__ prow, const StepScalars& sc, int n) {
   constexpr int E = L_t::E, T = L_t::T;
   const int t = L.t;
   bool far = false;
@@ -441,8 +466,7 @@ __device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const d
   for (int m = 0; m < E / 2; ++m) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const bool last = (h == 1 && m == E / 2 - 1);
-      if (last && t == T - 1) continue;       // B[N] = 0
+      if (2 * (t + T * m) + h >= n) continue;   // B[k] = 0 outside the line
       const int lane_off = 2 * t + h;
       const double uv = (urow + 2 * T * m)[lane_off];
       double gv = 0.0;
@@ -468,7 +492,7 @@ template <int MODE, class L_t>
 __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const V* __restrict__ srow,
                                           const double* __restrict__ urow, const double* __restrict__ prow,
                                           double* __restrict__ xo, bool live, const StepScalars& sc,
-                                          const FFTTables<double>& tab, const V* __restrict__ root2M) {
+                                          const FFTTables<double>& tab, const V* __restrict__ root2M, int n) {
   constexpr int M = L_t::M, E = L_t::E, T = L_t::T;
   const int t = L.t;
   // c2r pre-processing: Z[k] = FE[k] + i FO[k], FE = (X[k] + conj X[M-k])/2,
@@ -487,47 +511,45 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
   }, std::make_integer_sequence<int, E>{});
   L.template transform<+1>(d, smem, tab);
   // slot m holds z[j], j = t + T m: x[2j] = Re, x[2j+1] = Im; only j < M/2 (slots
-  // m < E/2) carry x[i] with i < M, and x[M-1] (j = M/2-1, odd part) is outside the grid
+  // m < E/2) carry x[i] with i < M, and x[i] with i >= N is outside the grid
   double* buf = reinterpret_cast<double*>(smem);
   if constexpr (MODE == 2) {
     if (live) {
 #pragma unroll
       for (int m = 0; m < E / 2; ++m) {
         const int j = t + T * m;
-        xo[2 * j] = sc.sigma * d[m].x;
-        if (m < E / 2 - 1 || t < T - 1) xo[2 * j + 1] = sc.sigma * d[m].y;
+        if (2 * j < n) xo[2 * j] = sc.sigma * d[m].x;
+        if (2 * j + 1 < n) xo[2 * j + 1] = sc.sigma * d[m].y;
       }
     }
     return false;
   } else {
-    // x[2j + h], j = t + T m: uniform base 2 T m, lane offset 2 t + h; x[N] (the last odd
-    // value of slot E/2-1 of lane T-1) is outside the grid and B[N] = 0
+    // x[2j + h], j = t + T m: uniform base 2 T m, lane offset 2 t + h; B[k] = 0 for k >= N
     // first sigma x (frees the transform's registers), then the pointwise terms are added
     // in place: each thread only touches its own LDS entries, so no barrier in between
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool last = (h == 1 && m == E / 2 - 1);
+        const int k = 2 * (t + T * m) + h;
         const double xv = h ? d[m].y : d[m].x;
-        L.put_real(buf, 2 * (t + T * m) + h, (last && t == T - 1) ? 0.0 : sc.sigma * xv);
+        L.put_real(buf, k, k < n ? sc.sigma * xv : 0.0);
       }
     }
     // one loop per kind of g (the kind is uniform: no per-element branches)
     bool far = false;   // some sin argument beyond the fast reduction's range
     switch (sc.gkind) {
-      case 1: far = add_pointwise<MODE, 1>(L, buf, urow, prow, sc); break;
-      case 2: add_pointwise<MODE, 2>(L, buf, urow, prow, sc); break;
-      case 3: add_pointwise<MODE, 3>(L, buf, urow, prow, sc); break;
-      default: add_pointwise<MODE, 0>(L, buf, urow, prow, sc); break;
+      case 1: far = add_pointwise<MODE, 1>(L, buf, urow, prow, sc, n); break;
+      case 2: add_pointwise<MODE, 2>(L, buf, urow, prow, sc, n); break;
+      case 3: add_pointwise<MODE, 3>(L, buf, urow, prow, sc, n); break;
+      default: add_pointwise<MODE, 0>(L, buf, urow, prow, sc, n); break;
     }
     if (sc.gkind == 1 && far) {
       // rare: replace the fast sine by the library's for the far arguments of this lane
 #pragma unroll 1
       for (int i = 0; i < E; ++i) {
         const int m = i >> 1, h = i & 1;
-        const bool last = (h == 1 && m == E / 2 - 1);
-        if (last && t == T - 1) continue;
+        if (2 * (t + T * m) + h >= n) continue;
         const double uv = (urow + 2 * T * m)[2 * t + h];
         if (!(fabs(uv) <= kSinFastMax)) {
           const int k = 2 * (t + T * m) + h;
@@ -560,9 +582,9 @@ __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int ld
   constexpr int RMODE = MODE >= 3 ? MODE - 3 : MODE;
   V d[E];
   if (!rhs_phase<RMODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
-                        RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M))
+                        RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n))
     return;
-  if constexpr (MODE < 3) gs_solve(L, d, smem, tab, gs);
+  if constexpr (MODE < 3) gs_solve(L, d, smem, tab, gs, n);
   if (live) {
     // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
 #pragma unroll
@@ -589,7 +611,7 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   double* xo = X + (size_t)yy * ldx;
   V d[E];
   rhs_phase<MODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
-                  MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M);
+                  MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n);
   mixed_solve(L, Lf, d, smem, tab, mx);
   if (live) {
 #pragma unroll
@@ -610,9 +632,9 @@ rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<
   const bool live = y < nlines;
   double* row = lines + (size_t)(live ? y : 0) * ld;
   V d[E];
-  load_line_pair<M, E, T>(d, row, 1, L.t);
-  gs_solve(L, d, smem, tab, gs);
-  if (live) store_line<M, E, T>(d, row, 1, L.t);
+  load_line_pair<M, E, T>(d, row, 1, L.t, n);
+  gs_solve(L, d, smem, tab, gs, n);
+  if (live) store_line<M, E, T>(d, row, 1, L.t, n);
 }
 
 // ----------------------------------------------------------------------------------
@@ -633,8 +655,8 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
   const int cc = live ? col : 0;
   const int t = L.t;
   V d[E];
-  load_column_pair<M, E, T>(L, d, X + cc, ldx, smem);
-  gs_solve(L, d, smem, tab, gs);
+  load_column_pair<M, E, T>(L, d, X + cc, ldx, smem, n);
+  gs_solve(L, d, smem, tab, gs, n);
   if (!live) return;
   const int o = t * ldu + col;
   if constexpr (MODE == 2) {
@@ -642,19 +664,19 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
     const int ox = t * ldx + col;
 #pragma unroll
     for (int m = 0; m < E; ++m)
-      if (m < E - 1 || t < T - 1) (X + T * m * ldx)[ox] = d[m].x;
+      if (t + T * m < n) (X + T * m * ldx)[ox] = d[m].x;
   } else {
-    // k = t + T m < N except m = E-1, t = T-1 (clamped load, no store)
-    const int oe = min(t, T - 2) * ldu + col;
+    // rows k = t + T m >= N: clamped loads, no store
     double uc[E], up[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      uc[m] = (ucur + T * m * ldu)[m == E - 1 ? oe : o];
-      if constexpr (MODE == 0) up[m] = (uprev + T * m * ldu)[m == E - 1 ? oe : o];
+      const int oc = (min(t + T * m, n - 1) - T * m) * ldu + col;
+      uc[m] = (ucur + T * m * ldu)[oc];
+      if constexpr (MODE == 0) up[m] = (uprev + T * m * ldu)[oc];
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if (m < E - 1 || t < T - 1) {
+      if (t + T * m < n) {
         if constexpr (MODE == 0) (uout + T * m * ldu)[o] = 2.0 * uc[m] - up[m] + d[m].x;
         else (uout + T * m * ldu)[o] = uc[m] + d[m].x;
       }
@@ -677,9 +699,9 @@ rows_gs_mixed_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTT
   const bool live = y < nlines;
   double* row = lines + (size_t)(live ? y : 0) * ld;
   V d[E];
-  load_line_pair<M, E, T>(d, row, 1, L.t);
+  load_line_pair<M, E, T>(d, row, 1, L.t, M - 1);
   mixed_solve(L, Lf, d, smem, tab, mx);
-  if (live) store_line<M, E, T>(d, row, 1, L.t);
+  if (live) store_line<M, E, T>(d, row, 1, L.t, M - 1);
 }
 
 template <int M, int MODE>
@@ -698,7 +720,7 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
   const bool live = col < n;
   const int cc = live ? col : 0;
   V d[E];
-  load_line_pair<M, E, T>(d, X + cc, ldx, L.t);
+  load_line_pair<M, E, T>(d, X + cc, ldx, L.t, M - 1);
   mixed_solve(L, Lf, d, smem, tab, mx);
   if (live) {
     const int o = L.t * ldu + col;
@@ -755,7 +777,7 @@ template <int M, int MODE>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_batched(const BatchInst* __restrict__ bi, int iu, int lds_, int ldx, int n, FFTTables<double> tab) {
   const BatchInst& p = bi[blockIdx.y];
-  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f};
+  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
   rows_rhs_gs_body<M, MODE>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M);
 }
 
@@ -769,7 +791,7 @@ template <int M>
 __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_batched(const BatchInst* __restrict__ bi, int ldx, int n, FFTTables<double> tab, int ngroups) {
   const BatchInst& p = bi[blockIdx.y];
-  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f};
+  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
   cols_gs_body<M, 2>(p.X, ldx, nullptr, nullptr, nullptr, n, n, tab, gs, ngroups);
 }
 

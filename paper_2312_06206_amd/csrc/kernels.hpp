@@ -14,7 +14,8 @@ template <typename R> struct GSTables {
   const V2<R>* q;        // Q = diag(e^{-i pi k / M}), k < M
   const V2<R>* lam_s;    // fft(Q s) / (2 p_1 M)
   const V2<R>* lam_c;    // fft(c) / M
-  const R* f;            // bordering correction (J c)[k] / p_1, k < N
+  const R* f;            // correction to H_N^-1: r = 1: (J c)[k] / p_1, k < N; else F, r rows of N
+  int r;                 // M - N
 };
 using GSTables64 = GSTables<double>;
 
@@ -156,6 +157,7 @@ struct BatchInst {
   const double2* lam_s;     // Gohberg-Semencul tables of this instance's H
   const double2* lam_c;
   const double* f;
+  int r;                    // M - N (the same for every instance of a launch)
   StepScalars sc;           // sigma, gamma carry this instance's kappa, h^-alpha, tau
 };
 

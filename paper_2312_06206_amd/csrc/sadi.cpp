@@ -37,10 +37,7 @@ bool finite_all(std::initializer_list<double> v) {
   return true;
 }
 
-bool supported_n(int n) {
-  const int m = n + 1;
-  return m >= 16 && m <= 4096 && (m & (m - 1)) == 0;
-}
+bool supported_n(int n) { return n >= 15 && n <= 4095; }
 
 sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2) {
   if (!domain) return fail(SADI_E_INVALID, "domain is NULL");
@@ -52,7 +49,7 @@ sadi_status validate_problem(double alpha, double kappa, int n, double tau, cons
   if (!(tau > 0.0)) return fail(SADI_E_INVALID, "tau must be positive");
   if (!(domain[1] > domain[0])) return fail(SADI_E_INVALID, "domain must satisfy b > a");
   if (n < 1) return fail(SADI_E_INVALID, "N must be >= 1");
-  if (!supported_n(n)) return fail(SADI_E_UNSUPPORTED, "N + 1 must be a power of two in [16, 4096]");
+  if (!supported_n(n)) return fail(SADI_E_UNSUPPORTED, "N must lie in [15, 4095]");
   return SADI_OK;
 }
 
@@ -105,7 +102,7 @@ template <int M> struct RowsGS {
 sadi::MixedTables mixed_tables(const sadi_ctx* c) {
   sadi::MixedTables mx{};
   mx.tab32 = sadi::FFTTables<float>{c->rootM32, c->rootS32, c->q32};
-  mx.gs32 = sadi::GSTables<float>{c->q32, c->lam_s32, c->lam_c32, c->f32};
+  mx.gs32 = sadi::GSTables<float>{c->q32, c->lam_s32, c->lam_c32, c->f32, 1};
   mx.toe = sadi::ToeplitzTables64{c->sig_e, c->sig_o};
   mx.q64 = c->root2M;
   mx.refine = c->prec == SADI_FP32_REFINE ? 1 : 0;
@@ -167,7 +164,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   sadi_ctx* c = new (std::nothrow) sadi_ctx();
   if (!c) return fail(SADI_E_NOMEM, "host allocation failed");
   c->n = n;
-  c->m = n + 1;
+  c->m = sadi::line_size(n);
+  c->r = c->m - n;
   c->alpha = alpha;
   c->kappa = kappa;
   c->tau = tau;
@@ -187,7 +185,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   // ---- host tables
   sadi::GSData gsd;
   try {
-    gsd = sadi::gs_data(a1, n, c->beta);
+    gsd = sadi::gs_data(a1, n, c->m, c->beta, g_setup_threads);
   } catch (const std::exception& e) {
     return bail(fail(SADI_E_INVALID, std::string("line matrix: ") + e.what()));
   }
@@ -212,7 +210,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   }
   c->ldlam = m + 1 + ((8 - (m + 1) % 8) % 8);
   std::vector<double> hlam((size_t)(m + 1) * c->ldlam, 0.0);
-  sadi::bccb_eigenvalues(a2, n, hlam.data(), c->ldlam, g_setup_threads);
+  sadi::bccb_eigenvalues(a2, n, m, hlam.data(), c->ldlam, g_setup_threads);
 
   // ---- mixed precision tables
   std::vector<float2> hrootM32(sh.T), hrootS32(sh.E), hq32(m), hls32(m), hlc32(m);
@@ -224,7 +222,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     hls32[k] = make_float2((float)hls[k].x, (float)hls[k].y);
     hlc32[k] = make_float2((float)hlc[k].x, (float)hlc[k].y);
   }
-  for (int k = 0; k < n; ++k) hf32[k] = (float)gsd.f[k];
+  if (c->r == 1)
+    for (int k = 0; k < n; ++k) hf32[k] = (float)gsd.f[k];   // FP32 solves: N = M - 1 only
   // beta T(a_0..a_{N-1}) embedded in a circulant of size P = 2M (first column a_0..a_{N-1},
   // three zeros, a_{N-1}..a_1); its eigenvalues split into even / odd frequencies
   std::vector<double> hsig_e(m), hsig_o(m);
@@ -252,7 +251,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->root2M, sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->lam_s, sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->lam_c, sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->f, sizeof(double) * n)) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->f, sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)n * c->ldS)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)n * c->ldX)) != SADI_OK) return bail(st);
@@ -276,7 +275,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->root2M, hroot2M.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->lam_s, hls.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->lam_c, hlc.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->f, gsd.f.data(), sizeof(double) * n)) != SADI_OK) return bail(st);
+  if ((st = up(c->f, gsd.f.data(), sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
   if ((st = up(c->lam2d, hlam.data(), sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
   if ((st = up(c->rootM32, hrootM32.data(), sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
   if ((st = up(c->rootS32, hrootS32.data(), sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
@@ -302,7 +301,7 @@ sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const doub
   sadi_status st = validate_problem(alpha, kappa, n, tau, domain, false);
   if (st != SADI_OK) return st;
   try {
-    const std::vector<double> a1 = sadi::riesz_coeffs(alpha, n + 1);
+    const std::vector<double> a1 = sadi::riesz_coeffs(alpha, sadi::line_size(n));
     const std::vector<double> a2 = sadi::laplacian_coeffs(alpha, n, g_setup_threads);
     return build_ctx(alpha, kappa, n, tau, domain, a1, a2, out);
   } catch (const std::bad_alloc&) {
@@ -319,6 +318,8 @@ sadi_status sadi_setup_with_coeffs(double alpha, double kappa, int n, double tau
   if (!a1 || !a2) return fail(SADI_E_INVALID, "coefficient table is NULL");
   sadi_status st = validate_problem(alpha, kappa, n, tau, domain, true);
   if (st != SADI_OK) return st;
+  if (sadi::line_size(n) != n + 1)
+    return fail(SADI_E_UNSUPPORTED, "injected coefficient tables need N + 1 to be a power of two");
   try {
     std::vector<double> v1(a1, a1 + n + 1), v2(a2, a2 + (size_t)n * n);
     return build_ctx(alpha, kappa, n, tau, domain, v1, v2, out);
@@ -334,6 +335,8 @@ sadi_status sadi_set_options(sadi_ctx* c, sadi_g_kind g, double g_param, sadi_pr
   if ((int)g < 0 || (int)g > 3) return fail(SADI_E_INVALID, "unknown g kind");
   if ((int)prec < 0 || (int)prec > 2) return fail(SADI_E_INVALID, "unknown precision");
   if (!std::isfinite(g_param)) return fail(SADI_E_INVALID, "g_param must be finite");
+  if (prec != SADI_FP64 && c->r != 1)
+    return fail(SADI_E_UNSUPPORTED, "float32 line solves need N + 1 to be a power of two");
   c->g = g;
   c->g_param = g_param;
   c->prec = prec;

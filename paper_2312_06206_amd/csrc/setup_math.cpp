@@ -336,11 +336,12 @@ void fft_inplace(std::vector<cld>& a, int sign) {
   }
 }
 
-GSData gs_data(const std::vector<double>& a1, int n, double beta) {
+GSData gs_data(const std::vector<double>& a1, int n, int m, double beta, int nthreads) {
   GSData g;
   g.n = n;
-  g.m = n + 1;
-  const int m = g.m;
+  g.m = m;
+  g.r = m - n;
+  if (g.r < 1 || (int)a1.size() < m) throw std::invalid_argument("line size must exceed N");
   std::vector<long double> t(m);
   for (int k = 0; k < m; ++k) t[k] = (k == 0 ? 1.0L : 0.0L) + (long double)beta * a1[k];
   g.c = toeplitz_first_column_inverse(t);
@@ -364,13 +365,53 @@ GSData gs_data(const std::vector<double>& a1, int n, double beta) {
     g.lam_c[k] = std::complex<double>((double)lc.real(), (double)lc.imag());
     g.lam_s[k] = std::complex<double>((double)ls.real(), (double)ls.imag());
   }
-  g.f.resize(n);
-  for (int k = 0; k < n; ++k) g.f[k] = (double)(g.c[m - 1 - k] / p1);
+  if (g.r == 1) {
+    g.f.resize(n);
+    for (int k = 0; k < n; ++k) g.f[k] = (double)(g.c[m - 1 - k] / p1);
+    return g;
+  }
+  // F = -H_N^-1 B column by column, H_N^-1 by the Gohberg-Semencul formula at size N:
+  //   H_N^-1 = (L(x) L(x)^T - L(y) L(y)^T) / x_0,  x = H_N^-1 e_1,  y = (0, x_{N-1}, ..., x_1)
+  // with L(v) the lower-triangular Toeplitz matrix of first column v
+  std::vector<long double> tn(t.begin(), t.begin() + n);
+  const std::vector<long double> xl = toeplitz_first_column_inverse(tn);
+  std::vector<double> x(n), y(n, 0.0);
+  for (int k = 0; k < n; ++k) x[k] = (double)xl[k];
+  for (int k = 1; k < n; ++k) y[k] = x[n - k];
+  const double x0 = x[0];
+  g.f.assign((size_t)g.r * n, 0.0);
+  parallel_for(g.r, worker_count(nthreads), [&](int j) {
+    std::vector<double> b(n), u(n), v(n), out(n);
+    for (int k = 0; k < n; ++k) b[k] = beta * a1[n + j - k];   // column j of H_M[0:N, N:M]
+    // u = L(x)^T b, v = L(y)^T b
+    for (int i = 0; i < n; ++i) {
+      double su = 0.0, sv = 0.0;
+      for (int k = i; k < n; ++k) {
+        su += x[k - i] * b[k];
+        sv += y[k - i] * b[k];
+      }
+      u[i] = su;
+      v[i] = sv;
+    }
+    // out = L(x) u - L(y) v
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k <= i; ++k) s += x[i - k] * u[k] - y[i - k] * v[k];
+      out[i] = s / x0;
+    }
+    for (int k = 0; k < n; ++k) g.f[(size_t)j * n + k] = -out[k];
+  });
   return g;
 }
 
-void bccb_eigenvalues(const std::vector<double>& a2, int n, double* out, int ld, int nthreads) {
-  const int m = n + 1, p = 2 * m;
+int line_size(int n) {
+  int m = 16;
+  while (m < n + 1) m *= 2;
+  return m;
+}
+
+void bccb_eigenvalues(const std::vector<double>& a2, int n, int m, double* out, int ld, int nthreads) {
+  const int p = 2 * m;
   const int nw = worker_count(nthreads);
   // pass 1: G[i][ky] = sum_j eps_j a_ij cos(2 pi j ky / P), ky in [0, M]; two rows per
   // complex transform (both transforms are real: even sequences)

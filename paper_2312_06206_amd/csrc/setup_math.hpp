@@ -25,18 +25,26 @@ void fft_inplace(std::vector<cld>& a, int sign);
 
 // Gohberg-Semencul data of the bordered line matrix H_M (M = N+1):
 //   lam_s = fft(Q s) / (2 p1 M), lam_c = fft(c) / M, f[k] = c[M-1-k] / p1 (k < N)
+// Gohberg-Semencul data of the line matrix H_M = I + beta T(a_0..a_{M-1}) (M a power of two,
+// M >= N + 1) and the correction from H_M^-1 to H_N^-1: with w = H_M^-1 [v; 0],
+//   H_N^-1 v = w[0:N] - F w[N:M],   F = A12 A22^-1 = -H_N^-1 B   (A = H_M^-1, B = H_M[0:N, N:M]).
+// r = M - N = 1: F is the vector f (f[k] = c[M-1-k] / c[0]); otherwise F is stored as r rows
+// of N (row j = column j of F).
 struct GSData {
-  int n = 0, m = 0;
+  int n = 0, m = 0, r = 0;
   std::vector<long double> c;            // H_M^-1 e_1
   std::vector<std::complex<double>> lam_s, lam_c;
-  std::vector<double> f;
+  std::vector<double> f;                 // r * n entries
 };
-GSData gs_data(const std::vector<double>& a1, int n, double beta);
+GSData gs_data(const std::vector<double>& a1, int n, int m, double beta, int nthreads = 0);
 
-// Eigenvalues of the P x P (P = 2M) block-circulant embedding of the N x N BTTB with
+// Eigenvalues of the P x P (P = 2M, M >= N + 1) block-circulant embedding of the N x N BTTB with
 // coefficients a2, divided by P^2, for kx, ky in [0, M].  Row kx of the result
 // (length M+1, at out[kx*ld ...]) is [Lam(kx, 0), Lam(kx, 2), ..., Lam(kx, M)]
 // followed by [Lam(kx, 1), Lam(kx, 3), ..., Lam(kx, M-1)] (even then odd ky).
-void bccb_eigenvalues(const std::vector<double>& a2, int n, double* out, int ld, int nthreads = 0);
+void bccb_eigenvalues(const std::vector<double>& a2, int n, int m, double* out, int ld, int nthreads = 0);
+
+// Line size for N interior nodes: the smallest power of two M >= max(N + 1, 16).
+int line_size(int n);
 
 }  // namespace sadi

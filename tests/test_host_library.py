@@ -70,7 +70,8 @@ def test_host_line_generator_is_first_column_of_inverse(alpha, n):
     ((1.5, 1.0, 63, 1e-3, (1.0, -1.0)), -1),      # b <= a
     ((1.5, 1.0, 63, float("nan"), (-1.0, 1.0)), -1),
     ((1.5, 1.0, 0, 1e-3, (-1.0, 1.0)), -1),       # N < 1
-    ((1.5, 1.0, 100, 1e-3, (-1.0, 1.0)), -4),     # N + 1 not a power of two
+    ((1.5, 1.0, 5000, 1e-3, (-1.0, 1.0)), -4),    # N above 4095
+    ((1.5, 1.0, 10, 1e-3, (-1.0, 1.0)), -4),      # N below 15
     ((1.5, 1.0, 8191, 1e-3, (-1.0, 1.0)), -4),    # too large
 ])
 def test_setup_rejects_bad_arguments_without_touching_the_gpu(args, status):
@@ -114,7 +115,7 @@ def test_batch_create_rejects_bad_arguments_without_touching_the_gpu():
     bad = np.array([1.5, 2.5])          # alpha outside (1, 2) for the second instance
     assert lib.sadi_batch_create(2, n, B._dptr(bad), B._dptr(ka), 1e-3, B._dptr(dom), 127, ctypes.byref(h)) == -1
     assert b"instance 1" in lib.sadi_last_error()
-    n_bad = (ctypes.c_int * 2)(63, 100)   # N + 1 not a power of two
+    n_bad = (ctypes.c_int * 2)(63, 5000)  # N above 4095
     assert lib.sadi_batch_create(2, n_bad, B._dptr(al), B._dptr(ka), 1e-3, B._dptr(dom), 127,
                                  ctypes.byref(h)) == -4
     assert not h.value
