@@ -275,13 +275,14 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
 // u = ucur, hat = the increment left in X by the y-sweep; the result overwrites uprev.
 template <int M, int LF>
 __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
-                int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
+                int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M,
+                int nrows) {
   using L_t = typename RowCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
   __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
   const L_t L(threadIdx.x);
   const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
-  const bool live = y < n;
+  const bool live = y < nrows;   // rows of n values each
   const int yy = live ? y : 0;
   const double* row = u + (size_t)yy * ldu;
   double* prow = LF ? uprev + (size_t)yy * ldu : nullptr;
@@ -744,13 +745,13 @@ template <int M, int LF>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
-  rows_fwd_body<M, LF>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M);
+  rows_fwd_body<M, LF>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M, n);
 }
 template <int M, int LF>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_fwd_batched(const BatchInst* __restrict__ bi, int iu, int ip, int ldx, int lds_, int n, FFTTables<double> tab) {
   const BatchInst& p = bi[blockIdx.y];
-  rows_fwd_body<M, LF>(p.u[iu], p.u[ip], p.X, ldx, n, p.S, lds_, n, tab, tab.root2M);
+  rows_fwd_body<M, LF>(p.u[iu], p.u[ip], p.X, ldx, n, p.S, lds_, n, tab, tab.root2M, n);
 }
 
 template <int M>
@@ -920,6 +921,54 @@ void launch_adjoint_combine(double ca, double c2, double kappa, int gkind, doubl
 void launch_adjoint_finish(const double* partial, int nrows, double c2, double kappa, double* dkappa,
                            hipStream_t st) {
   hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, st, partial, nrows, c2, kappa, dkappa);
+}
+
+
+// ----------------------------------------------------------------------------------
+// Eigenvalues of the block-circulant embedding (set-up).  The embedding of a_ij is even in
+// both directions, so each 1D transform of it is 2 Re(transform of the zero-padded half) -
+// (the value at 0): first over j for every row i, then over i.
+template <int M>
+__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+rows_fwd_rect_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int nrows, int nlen,
+                     FFTTables<double> tab) {
+  rows_fwd_body<M, 0>(u, nullptr, nullptr, 0, ldu, S, lds_, nlen, tab, tab.root2M, nrows);
+}
+
+// G(i, k) = 2 Re S[i][k] - a_i0 for i < n, k <= M, stored transposed: GT[k][i]
+__global__ void __launch_bounds__(256)
+bccb_pass1_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ a2, int n, int m,
+                  double* __restrict__ GT, int ldg) {
+  const int k = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  if (k > m) return;
+  GT[(size_t)k * ldg + i] = 2.0 * S[(size_t)i * lds_ + k].x - a2[i];
+}
+
+// Lambda(kx, ky) = (2 Re T[ky][kx] - G(0, ky)) * scale, row kx of lam: even ky at ky/2, odd
+// ky at M/2 + 1 + (ky - 1)/2
+__global__ void __launch_bounds__(256)
+bccb_pass2_kernel(const V* __restrict__ Tsp, int ldt, const double* __restrict__ GT, int ldg, int m,
+                  double* __restrict__ lam, int ldlam, double scale) {
+  const int kx = blockIdx.x * 256 + threadIdx.x, ky = blockIdx.y;
+  if (kx > m) return;
+  const int pos = (ky % 2 == 0) ? ky / 2 : m / 2 + 1 + (ky - 1) / 2;
+  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[(size_t)ky * ldt + kx].x - GT[(size_t)ky * ldg]) * scale;
+}
+
+template <int M>
+void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg, V* work_spec, int ldt,
+                             double* lam, int ldlam, const FFTTables<double>& tab, hipStream_t st) {
+  // pass 1: transforms of the rows of a2 (n rows of n) into work_spec (n rows, pitch ldt)
+  hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW),
+                     dim3(RowCfg<M>::NT), 0, st, a2, n, work_spec, ldt, n, n, tab);
+  hipLaunchKernelGGL(bccb_pass1_kernel, dim3((M + 1 + 255) / 256, n), dim3(256), 0, st, work_spec, ldt, a2, n, M,
+                     work_real, ldg);
+  // pass 2: transforms of the M + 1 rows of G^T (n values each)
+  hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((M + 1 + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW),
+                     dim3(RowCfg<M>::NT), 0, st, work_real, ldg, work_spec, ldt, M + 1, n, tab);
+  const double p = 2.0 * M;
+  hipLaunchKernelGGL(bccb_pass2_kernel, dim3((M + 1 + 255) / 256, M + 1), dim3(256), 0, st, work_spec, ldt, work_real,
+                     ldg, M, lam, ldlam, 1.0 / (p * p));
 }
 
 // ----------------------------------------------------------------------------------
@@ -1107,7 +1156,9 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
                                           hipStream_t);                                                           \
   template void launch_batch_rows_rhs<M>(int, const BatchInst*, int, int, int, int, int, const FFTTables<double>&, \
                                          hipStream_t);                                                            \
-  template void launch_batch_cols_gs<M>(const BatchInst*, int, int, int, const FFTTables<double>&, hipStream_t);
+  template void launch_batch_cols_gs<M>(const BatchInst*, int, int, int, const FFTTables<double>&, hipStream_t); \
+  template void launch_bccb_eigenvalues<M>(const double*, int, double*, int, V*, int, double*, int,              \
+                                           const FFTTables<double>&, hipStream_t);
 
 SADI_FOR_EACH_M(SADI_INSTANTIATE)
 

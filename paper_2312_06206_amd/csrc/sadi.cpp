@@ -93,6 +93,11 @@ template <int M> struct RowsFwdPitched {  // spectrum of a grid function with ro
     sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, ld, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
   }
 };
+template <int M> struct BccbEig {
+  static void run(const sadi_ctx* c, const double* a2d, double* gt, double2* spec) {
+    sadi::launch_bccb_eigenvalues<M>(a2d, c->n, gt, c->n, spec, c->ldS, c->lam2d, c->ldlam, tables(c), c->stream);
+  }
+};
 template <int M> struct RowsGS {
   static void run(const sadi_ctx* c, double* lines, int ld, int nlines) {
     sadi::launch_rows_gs<M>(lines, ld, nlines, c->n, tables(c), gs_tables(c), c->stream);
@@ -209,8 +214,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     hlc[k] = make_double2(gsd.lam_c[k].real(), gsd.lam_c[k].imag());
   }
   c->ldlam = m + 1 + ((8 - (m + 1) % 8) % 8);
-  std::vector<double> hlam((size_t)(m + 1) * c->ldlam, 0.0);
-  sadi::bccb_eigenvalues(a2, n, m, hlam.data(), c->ldlam, g_setup_threads);
+  const size_t lam_elems = (size_t)(m + 1) * c->ldlam;
 
   // ---- mixed precision tables
   std::vector<float2> hrootM32(sh.T), hrootS32(sh.E), hq32(m), hls32(m), hlc32(m);
@@ -252,7 +256,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->lam_s, sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->lam_c, sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->f, sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
+  if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * lam_elems)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)n * c->ldS)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)n * c->ldX)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootM32, sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
@@ -276,7 +280,6 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->lam_s, hls.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->lam_c, hlc.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->f, gsd.f.data(), sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
-  if ((st = up(c->lam2d, hlam.data(), sizeof(double) * hlam.size())) != SADI_OK) return bail(st);
   if ((st = up(c->rootM32, hrootM32.data(), sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
   if ((st = up(c->rootS32, hrootS32.data(), sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
   if ((st = up(c->q32, hq32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
@@ -285,6 +288,39 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->f32, hf32.data(), sizeof(float) * n)) != SADI_OK) return bail(st);
   if ((st = up(c->sig_e, hsig_e.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->sig_o, hsig_o.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
+
+  // ---- eigenvalues of the block-circulant embedding of L_h, on the device with the row
+  // transform: two passes of even-extension DFTs over the uploaded a_ij (temporaries freed)
+  {
+    double* a2d = nullptr;
+    double* gt = nullptr;
+    double2* spec = nullptr;
+    auto tmp = [&](void** p, size_t bytes) -> sadi_status {
+      hipError_t e = hipMalloc(p, bytes);
+      if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(SADI_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+      }
+      return SADI_OK;
+    };
+    auto drop = [&]() {
+      if (a2d) (void)hipFree(a2d);
+      if (gt) (void)hipFree(gt);
+      if (spec) (void)hipFree(spec);
+    };
+    if ((st = tmp((void**)&a2d, sizeof(double) * a2.size())) != SADI_OK ||
+        (st = tmp((void**)&gt, sizeof(double) * (size_t)(m + 1) * n)) != SADI_OK ||
+        (st = tmp((void**)&spec, sizeof(double2) * (size_t)(m + 1) * c->ldS)) != SADI_OK ||
+        (st = up(a2d, a2.data(), sizeof(double) * a2.size())) != SADI_OK) {
+      drop();
+      return bail(st);
+    }
+    dispatch_m<BccbEig>(m, c, a2d, gt, spec);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    drop();
+    if (e != hipSuccess) return bail(fail(SADI_E_DEVICE, std::string("eigenvalue set-up: ") + hipGetErrorString(e)));
+  }
   *out = c;
   return SADI_OK;
 }

@@ -410,52 +410,5 @@ int line_size(int n) {
   return m;
 }
 
-void bccb_eigenvalues(const std::vector<double>& a2, int n, int m, double* out, int ld, int nthreads) {
-  const int p = 2 * m;
-  const int nw = worker_count(nthreads);
-  // pass 1: G[i][ky] = sum_j eps_j a_ij cos(2 pi j ky / P), ky in [0, M]; two rows per
-  // complex transform (both transforms are real: even sequences)
-  std::vector<double> G((size_t)n * (m + 1));
-  const int npairs1 = (n + 1) / 2;
-  parallel_for(npairs1, nw, [&](int pr) {
-    const int i0 = 2 * pr, i1 = 2 * pr + 1;
-    std::vector<cld> buf(p, cld(0, 0));
-    for (int j = 0; j < n; ++j) {
-      const long double re = a2[(size_t)j * n + i0];
-      const long double im = i1 < n ? a2[(size_t)j * n + i1] : 0.0;
-      buf[j] = cld(re, im);
-      if (j > 0) buf[p - j] = cld(re, im);
-    }
-    fft_inplace(buf, -1);
-    for (int ky = 0; ky <= m; ++ky) {
-      G[(size_t)i0 * (m + 1) + ky] = (double)buf[ky].real();
-      if (i1 < n) G[(size_t)i1 * (m + 1) + ky] = (double)buf[ky].imag();
-    }
-  });
-  // pass 2: Lam[kx][ky] = sum_i eps_i G[i][ky] cos(2 pi i kx / P); two ky per transform
-  const long double scale = 1.0L / ((long double)p * p);
-  const int npairs2 = (m + 2) / 2;
-  parallel_for(npairs2, nw, [&](int pr) {
-    const int k0 = 2 * pr, k1 = 2 * pr + 1;
-    std::vector<cld> buf(p, cld(0, 0));
-    for (int i = 0; i < n; ++i) {
-      const long double re = G[(size_t)i * (m + 1) + k0];
-      const long double im = k1 <= m ? G[(size_t)i * (m + 1) + k1] : 0.0;
-      buf[i] = cld(re, im);
-      if (i > 0) buf[p - i] = cld(re, im);
-    }
-    fft_inplace(buf, -1);
-    for (int kx = 0; kx <= m; ++kx) {
-      double* row = out + (size_t)kx * ld;
-      auto put = [&](int ky, long double v) {
-        // even ky -> position ky/2, odd ky -> M/2 + 1 + (ky-1)/2
-        const int pos = (ky % 2 == 0) ? ky / 2 : m / 2 + 1 + (ky - 1) / 2;
-        row[pos] = (double)(v * scale);
-      };
-      put(k0, buf[kx].real());
-      if (k1 <= m) put(k1, buf[kx].imag());
-    }
-  });
-}
 
 }  // namespace sadi

@@ -38,11 +38,6 @@ struct GSData {
 };
 GSData gs_data(const std::vector<double>& a1, int n, int m, double beta, int nthreads = 0);
 
-// Eigenvalues of the P x P (P = 2M, M >= N + 1) block-circulant embedding of the N x N BTTB with
-// coefficients a2, divided by P^2, for kx, ky in [0, M].  Row kx of the result
-// (length M+1, at out[kx*ld ...]) is [Lam(kx, 0), Lam(kx, 2), ..., Lam(kx, M)]
-// followed by [Lam(kx, 1), Lam(kx, 3), ..., Lam(kx, M-1)] (even then odd ky).
-void bccb_eigenvalues(const std::vector<double>& a2, int n, int m, double* out, int ld, int nthreads = 0);
 
 // Line size for N interior nodes: the smallest power of two M >= max(N + 1, 16).
 int line_size(int n);
