@@ -985,19 +985,27 @@ void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx,
                        lds_, n, tab, root2M);
 }
 
-// out = 2 ucur - uprev + hat (mode 0, out may alias uprev) or out = ucur + hat (mode 1)
+// out = 2 ucur - uprev + hat (mode 0, out may alias uprev), out = ucur + hat (mode 1), or
+// (ucur, uprev) <- (2 ucur - uprev + hat, ucur) (mode 2)
 __global__ void __launch_bounds__(256)
-leapfrog_kernel(int mode, const double* ucur, const double* uprev, const double* __restrict__ hat, int ldx,
-                double* out, int n) {
+leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict__ hat, int ldx, double* out,
+                int n) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   if (i >= n) return;
   const size_t o = (size_t)j * n + i;
   const double h = hat[(size_t)j * ldx + i];
-  out[o] = mode == 0 ? 2.0 * ucur[o] - uprev[o] + h : ucur[o] + h;
+  const double c = ucur[o];
+  if (mode == 2) {           // newest into ucur, the current state into uprev
+    const double v = 2.0 * c - uprev[o] + h;
+    uprev[o] = c;
+    ucur[o] = v;
+  } else {
+    out[o] = mode == 0 ? 2.0 * c - uprev[o] + h : c + h;
+  }
 }
 
-void launch_leapfrog(int mode, const double* ucur, const double* uprev, const double* hat, int ldx, double* out,
-                     int n, hipStream_t st) {
+void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, double* out, int n,
+                     hipStream_t st) {
   hipLaunchKernelGGL(leapfrog_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, mode, ucur, uprev, hat, ldx, out, n);
 }
 

@@ -165,8 +165,8 @@ struct BatchInst {
 template <int M>
 void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, double2* S, int lds_,
                      int n, const FFTTables<double>& tab, const double2* root2M, hipStream_t st);
-void launch_leapfrog(int mode, const double* ucur, const double* uprev, const double* hat, int ldx, double* out,
-                     int n, hipStream_t st);
+void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, double* out, int n,
+                     hipStream_t st);
 template <int M>
 void launch_cols_conv(double2* S, int lds_, int n, const double* lam, int ldlam, const FFTTables<double>& tab,
                       const double2* root2M, hipStream_t st);

@@ -414,16 +414,17 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
       if (st != SADI_OK) return st;
       if (s > 0) std::swap(a, b);
     }
-    sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
-    sadi_status st = check_launch();
+    // the pending update leaves the newest state in u_cur and the one before in u_prev
+    if (b == u_cur)
+      sadi::launch_leapfrog(2, b, a, c->X, c->ldX, nullptr, c->n, c->stream);
+    else
+      sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
+    return check_launch();
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    sadi_status st = enqueue_step(c, 0, b, a, nullptr, a);
     if (st != SADI_OK) return st;
     std::swap(a, b);
-  } else {
-    for (int s = 0; s < nsteps; ++s) {
-      sadi_status st = enqueue_step(c, 0, b, a, nullptr, a);
-      if (st != SADI_OK) return st;
-      std::swap(a, b);
-    }
   }
   if (nsteps % 2 == 1) {
     // newest is in u_prev's buffer: exchange the two arrays through the X workspace
