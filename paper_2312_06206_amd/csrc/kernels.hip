@@ -32,6 +32,20 @@ using V = double2;
 #define SADI_OCC2 __attribute__((amdgpu_waves_per_eu(1, 8)))
 
 // ----------------------------------------------------------------------------------
+// The half spectrum S keeps its rows in interleaved pairs: S(y, k) is complex element
+// ((y >> 1) ldS + k) 2 + (y & 1), so rows y and y + 1 of one column share 32 contiguous
+// bytes and the column passes fetch two rows per memory request.  spec_row(y) is the
+// offset of S(y, 0); the elements of a row then lie 2 apart.
+__device__ __forceinline__ size_t spec_row(int y, int lds_) { return (size_t)(y >> 1) * 2 * lds_ + (y & 1); }
+
+// Row kernels of one row per workgroup: blocks 16 q + j and 16 q + 8 + j (j < 8) take rows
+// 2 (8 q + j) and 2 (8 q + j) + 1, and dispatch sends both to the same XCD, whose L2 then
+// holds the whole lines of S that the pair shares.  The grid is a multiple of 16.
+__device__ __forceinline__ int paired_row_block() {
+  const int b = blockIdx.x;
+  return (((b >> 4) << 3) | (b & 7)) * 2 + ((b >> 3) & 1);
+}
+
 // XCD-aware block order for column kernels: consecutive dispatch slots go to the 8
 // XCDs round robin, so give the blocks of one XCD adjacent column groups (their row
 // segments then share L2 lines).
@@ -277,11 +291,11 @@ template <int M, int LF>
 __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M,
                 int nrows) {
-  using L_t = typename RowCfg<M>::Line;
+  using L_t = typename RowFwdCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
+  __shared__ __align__(16) unsigned char smem[RowFwdCfg<M>::LDS_BYTES];
   const L_t L(threadIdx.x);
-  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
+  const int y = blockIdx.x * RowFwdCfg<M>::LPW + L.line;
   const bool live = y < nrows;   // rows of n values each
   const int yy = live ? y : 0;
   const double* row = u + (size_t)yy * ldu;
@@ -317,13 +331,13 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
   // pair Z[k] with Z[M-k] through a half-length complex buffer in two rounds: slots
   // m < E/2 hold k < M/2, the others k >= M/2; k = 0 and k = M/2 are their own partners.
   V* zb = reinterpret_cast<V*>(smem);
-  V* out = S + (size_t)(live ? y : 0) * lds_;
+  V* out = S + spec_row(live ? y : 0, lds_);   // element k at out[2 k]
   auto emit = [&](int k, V zk, V zmk) {
     const V zm = cconj(zmk);
     const V ev = cscale(cadd(zk, zm), 0.5);
     const V od = cscale(csub(zk, zm), 0.5);        // = i * FO[k]
     const V fo = V{od.y, -od.x};                   // X[k] = FE[k] + W_P^k FO[k]
-    if (live) out[k] = cadd(ev, cmul(fo, root2M[k]));
+    if (live) out[2 * k] = cadd(ev, cmul(fo, root2M[k]));
   };
 #pragma unroll
   for (int round = 0; round < 2; ++round) {
@@ -343,7 +357,7 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
       if (lower != (round == 0)) {
         if (k == 0) {
           emit(0, d[c], d[c]);
-          if (live) out[M] = V{d[c].x - d[c].y, 0.0};   // X[M] = Re Z0 - Im Z0
+          if (live) out[2 * M] = V{d[c].x - d[c].y, 0.0};   // X[M] = Re Z0 - Im Z0
         } else if (k == M / 2) {
           emit(k, d[c], d[c]);
         } else {
@@ -399,7 +413,9 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int y = t + T * m;   // rows y >= N are the zero padding (clamped, unused load)
-    const V v = (S + T * m * lds_)[(min(y, n - 1) - T * m) * lds_ + colc];
+    const int yc = min(y, n - 1);
+    // S(yc, colc) from the uniform base of rows T m (T m is even)
+    const V v = (S + T * m * lds_)[((yc - T * m) >> 1) * 2 * lds_ + 2 * colc + (yc & 1)];
     d[m] = y < n ? v : V{0.0, 0.0};
   }
   // odd lines: W_P^y = e^{-i pi y/M} on the input, y = t + T m: the per-slot part
@@ -440,7 +456,7 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
   }
   __syncthreads();
   if (!odd && live) {
-    const int wo = t * lds_ + col;
+    const int wo = (t >> 1) * 2 * lds_ + 2 * col + (t & 1);   // S(t + T m, col)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       if (t + T * m < n) (S + T * m * lds_)[wo] = cadd(d[m], (xb + T * CPW * m)[xo]);
@@ -498,13 +514,13 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
   const int t = L.t;
   // c2r pre-processing: Z[k] = FE[k] + i FO[k], FE = (X[k] + conj X[M-k])/2,
   // FO = W_P^{-k} (X[k] - conj X[M-k])/2 ; the 1/2 is folded into Lambda.
-  // X[M-k] with M-k = (M - T m) - t: uniform base minus the lane index
+  // X[M-k] with M-k = (M - T m) - t: uniform base minus the lane index (srow elements 2 apart)
   // W_P^{-k}, k = t + T m: e^{i pi t/M} (conjugate of root2M[t]) times e^{i pi m/E}
   const V s0 = root2M[t];
   for_slots([&](auto mc) {
     constexpr int m = decltype(mc)::value;
-    const V xk = (srow + T * m)[t];
-    const V c = cconj((srow + (M - T * m))[-t]);
+    const V xk = (srow + 2 * T * m)[2 * t];
+    const V c = cconj((srow + 2 * (M - T * m))[-2 * t]);
     const V fe = cadd(xk, c);
     const V fo = shift16<+1, m * (16 / E)>(cmulc(csub(xk, c), s0));
     d[m] = V{fe.x - fo.y, fe.y + fo.x};
@@ -575,14 +591,16 @@ __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int ld
   constexpr int E = L_t::E, T = L_t::T;
   __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
   const L_t L(threadIdx.x);
-  const int y = blockIdx.x * RowCfg<M>::LPW + L.line;
+  constexpr bool PAIRED = RowCfg<M>::LPW == 1;
+  const int y = (PAIRED ? paired_row_block() : (int)blockIdx.x) * RowCfg<M>::LPW + L.line;
+  if (PAIRED && y >= n) return;   // a whole workgroup past the last row
   const bool live = y < n;
   const int yy = live ? y : 0;
   double* xo = X + (size_t)yy * ldx;
   // MODE 3 / 4: as 0 / 1 but X = B (no line solve; the dense-inverse path follows)
   constexpr int RMODE = MODE >= 3 ? MODE - 3 : MODE;
   V d[E];
-  if (!rhs_phase<RMODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
+  if (!rhs_phase<RMODE>(L, d, smem, S + spec_row(yy, lds_), u + (size_t)yy * ldu,
                         RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n))
     return;
   if constexpr (MODE < 3) gs_solve(L, d, smem, tab, gs, n);
@@ -611,7 +629,7 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   const int yy = live ? y : 0;
   double* xo = X + (size_t)yy * ldx;
   V d[E];
-  rhs_phase<MODE>(L, d, smem, S + (size_t)yy * lds_, u + (size_t)yy * ldu,
+  rhs_phase<MODE>(L, d, smem, S + spec_row(yy, lds_), u + (size_t)yy * ldu,
                   MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n);
   mixed_solve(L, Lf, d, smem, tab, mx);
   if (live) {
@@ -742,13 +760,13 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
 // kernels: one instance (pointer arguments) and batched (instance blockIdx.y of an
 // array of BatchInst sharing N, pitches and line tables; iu / ip pick the state buffers)
 template <int M, int LF>
-__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+__global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
   rows_fwd_body<M, LF>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M, n);
 }
 template <int M, int LF>
-__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+__global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_batched(const BatchInst* __restrict__ bi, int iu, int ip, int ldx, int lds_, int n, FFTTables<double> tab) {
   const BatchInst& p = bi[blockIdx.y];
   rows_fwd_body<M, LF>(p.u[iu], p.u[ip], p.X, ldx, n, p.S, lds_, n, tab, tab.root2M, n);
@@ -929,7 +947,7 @@ void launch_adjoint_finish(const double* partial, int nrows, double c2, double k
 // both directions, so each 1D transform of it is 2 Re(transform of the zero-padded half) -
 // (the value at 0): first over j for every row i, then over i.
 template <int M>
-__global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
+__global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_rect_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int nrows, int nlen,
                      FFTTables<double> tab) {
   rows_fwd_body<M, 0>(u, nullptr, nullptr, 0, ldu, S, lds_, nlen, tab, tab.root2M, nrows);
@@ -941,7 +959,7 @@ bccb_pass1_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ 
                   double* __restrict__ GT, int ldg) {
   const int k = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
   if (k > m) return;
-  GT[(size_t)k * ldg + i] = 2.0 * S[(size_t)i * lds_ + k].x - a2[i];
+  GT[(size_t)k * ldg + i] = 2.0 * S[spec_row(i, lds_) + 2 * k].x - a2[i];
 }
 
 // Lambda(kx, ky) = (2 Re T[ky][kx] - G(0, ky)) * scale, row kx of lam: even ky at ky/2, odd
@@ -952,20 +970,20 @@ bccb_pass2_kernel(const V* __restrict__ Tsp, int ldt, const double* __restrict__
   const int kx = blockIdx.x * 256 + threadIdx.x, ky = blockIdx.y;
   if (kx > m) return;
   const int pos = (ky % 2 == 0) ? ky / 2 : m / 2 + 1 + (ky - 1) / 2;
-  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[(size_t)ky * ldt + kx].x - GT[(size_t)ky * ldg]) * scale;
+  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[spec_row(ky, ldt) + 2 * kx].x - GT[(size_t)ky * ldg]) * scale;
 }
 
 template <int M>
 void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg, V* work_spec, int ldt,
                              double* lam, int ldlam, const FFTTables<double>& tab, hipStream_t st) {
   // pass 1: transforms of the rows of a2 (n rows of n) into work_spec (n rows, pitch ldt)
-  hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW),
-                     dim3(RowCfg<M>::NT), 0, st, a2, n, work_spec, ldt, n, n, tab);
+  hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((n + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW),
+                     dim3(RowFwdCfg<M>::NT), 0, st, a2, n, work_spec, ldt, n, n, tab);
   hipLaunchKernelGGL(bccb_pass1_kernel, dim3((M + 1 + 255) / 256, n), dim3(256), 0, st, work_spec, ldt, a2, n, M,
                      work_real, ldg);
   // pass 2: transforms of the M + 1 rows of G^T (n values each)
-  hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((M + 1 + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW),
-                     dim3(RowCfg<M>::NT), 0, st, work_real, ldg, work_spec, ldt, M + 1, n, tab);
+  hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((M + 1 + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW),
+                     dim3(RowFwdCfg<M>::NT), 0, st, work_real, ldg, work_spec, ldt, M + 1, n, tab);
   const double p = 2.0 * M;
   hipLaunchKernelGGL(bccb_pass2_kernel, dim3((M + 1 + 255) / 256, M + 1), dim3(256), 0, st, work_spec, ldt, work_real,
                      ldg, M, lam, ldlam, 1.0 / (p * p));
@@ -976,13 +994,13 @@ void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg
 template <int M>
 void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, V* S, int lds_, int n,
                      const FFTTables<double>& tab, const V* root2M, hipStream_t st) {
-  const int grid = (n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
+  const int grid = (n + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW;
   if (hat == nullptr)
-    hipLaunchKernelGGL((rows_fwd_kernel<M, 0>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu, S,
-                       lds_, n, tab, root2M);
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 0>), dim3(grid), dim3(RowFwdCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu,
+                       S, lds_, n, tab, root2M);
   else
-    hipLaunchKernelGGL((rows_fwd_kernel<M, 1>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu, S,
-                       lds_, n, tab, root2M);
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 1>), dim3(grid), dim3(RowFwdCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu,
+                       S, lds_, n, tab, root2M);
 }
 
 // out = 2 ucur - uprev + hat (mode 0, out may alias uprev), out = ucur + hat (mode 1), or
@@ -1019,11 +1037,18 @@ void launch_cols_conv(V* S, int lds_, int n, const double* lam, int ldlam, const
                      tab, root2M, ngroups);
 }
 
+// blocks of rows_rhs_gs: one row per block is launched in paired order (multiple of 16)
+template <int M>
+int rhs_grid(int n) {
+  const int g = (n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
+  return RowCfg<M>::LPW == 1 ? (g + 15) / 16 * 16 : g;
+}
+
 template <int M>
 void launch_rows_rhs_gs(int mode, const V* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
                         int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const GSTables64& gs,
                         const V* root2M, hipStream_t st) {
-  const int grid = (n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW;
+  const int grid = rhs_grid<M>(n);
   if (mode == 0)
     hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
                        ldx, n, sc, tab, gs, root2M);
@@ -1098,11 +1123,12 @@ void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur
 template <int M>
 void launch_batch_rows_fwd(int lf, const BatchInst* bi, int count, int iu, int ip, int ldx, int lds_, int n,
                            const FFTTables<double>& tab, hipStream_t st) {
-  const dim3 grid((n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW, count);
+  const dim3 grid((n + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW, count);
+  const dim3 blk(RowFwdCfg<M>::NT);
   if (lf)
-    hipLaunchKernelGGL((rows_fwd_batched<M, 1>), grid, dim3(RowCfg<M>::NT), 0, st, bi, iu, ip, ldx, lds_, n, tab);
+    hipLaunchKernelGGL((rows_fwd_batched<M, 1>), grid, blk, 0, st, bi, iu, ip, ldx, lds_, n, tab);
   else
-    hipLaunchKernelGGL((rows_fwd_batched<M, 0>), grid, dim3(RowCfg<M>::NT), 0, st, bi, iu, ip, ldx, lds_, n, tab);
+    hipLaunchKernelGGL((rows_fwd_batched<M, 0>), grid, blk, 0, st, bi, iu, ip, ldx, lds_, n, tab);
 }
 
 template <int M>
@@ -1117,7 +1143,7 @@ void launch_batch_cols_conv(const BatchInst* bi, int count, int lds_, int n, int
 template <int M>
 void launch_batch_rows_rhs(int mode, const BatchInst* bi, int count, int iu, int lds_, int ldx, int n,
                            const FFTTables<double>& tab, hipStream_t st) {
-  const dim3 grid((n + RowCfg<M>::LPW - 1) / RowCfg<M>::LPW, count);
+  const dim3 grid(rhs_grid<M>(n), count);
   const dim3 blk(RowCfg<M>::NT);
   switch (mode) {
     case 0: hipLaunchKernelGGL((rows_rhs_gs_batched<M, 0>), grid, blk, 0, st, bi, iu, lds_, ldx, n, tab); break;

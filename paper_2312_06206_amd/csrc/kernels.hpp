@@ -94,6 +94,18 @@ template <int M> struct RowCfg {
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
 };
 
+// forward row transforms: at T = 256 both rows of a pair of the half spectrum in one
+// workgroup, lanes interleaved, so that every store covers whole cache lines of S
+template <int M> struct RowFwdCfg {
+  static constexpr int T = M / Shape<M>::E;
+  static constexpr int LPW = T >= 256 ? 2 : 256 / T;
+  static constexpr bool LINE_FAST = T >= 256;
+  static constexpr int SPLIT = 2;
+  using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
+  static constexpr int NT = Line::NT;
+  static constexpr int LDS_BYTES = Line::LDS_BYTES;
+};
+
 // two lines (even / odd frequency halves) per column, 512 threads per workgroup
 template <int M> struct ColConvCfg {
   static constexpr int T = M / Shape<M>::E;

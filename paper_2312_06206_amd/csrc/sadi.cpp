@@ -247,7 +247,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   }
 
   // ---- device allocations
-  c->ldS = m + 8;           // complex elements per row of the half spectrum (>= M+1)
+  c->ldS = m + 8;           // complex elements per row of the half spectrum (>= M+1); rows in pairs
   c->ldX = m;
   sadi_status st;
   if ((st = c->alloc((void**)&c->rootM, sizeof(double2) * sh.T)) != SADI_OK) return bail(st);
@@ -257,7 +257,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->lam_c, sizeof(double2) * m)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->f, sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * lam_elems)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)n * c->ldS)) != SADI_OK) return bail(st);
+  // rows stored in interleaved pairs: ceil(N / 2) pairs of 2 ldS complex values
+  if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)(n + 1) * c->ldS)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)n * c->ldX)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootM32, sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootS32, sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
@@ -310,7 +311,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     };
     if ((st = tmp((void**)&a2d, sizeof(double) * a2.size())) != SADI_OK ||
         (st = tmp((void**)&gt, sizeof(double) * (size_t)(m + 1) * n)) != SADI_OK ||
-        (st = tmp((void**)&spec, sizeof(double2) * (size_t)(m + 1) * c->ldS)) != SADI_OK ||
+        (st = tmp((void**)&spec, sizeof(double2) * (size_t)(m + 2) * c->ldS)) != SADI_OK ||
         (st = up(a2d, a2.data(), sizeof(double) * a2.size())) != SADI_OK) {
       drop();
       return bail(st);
