@@ -32,11 +32,15 @@ using V = double2;
 #define SADI_OCC2 __attribute__((amdgpu_waves_per_eu(1, 8)))
 
 // ----------------------------------------------------------------------------------
-// The half spectrum S keeps its rows in interleaved pairs: S(y, k) is complex element
-// ((y >> 1) ldS + k) 2 + (y & 1), so rows y and y + 1 of one column share 32 contiguous
-// bytes and the column passes fetch two rows per memory request.  spec_row(y) is the
-// offset of S(y, 0); the elements of a row then lie 2 apart.
-__device__ __forceinline__ size_t spec_row(int y, int lds_) { return (size_t)(y >> 1) * 2 * lds_ + (y & 1); }
+// Paired row layout: rows y and y + 1 (y even) interleaved, element (y, k) at
+// ((y >> 1) ld + k) 2 + (y & 1) for a row pitch of ld elements.  A column pass then fetches
+// two rows of a column per memory request.  The half spectrum S always uses it; the y-sweep
+// increment X of a single instance uses it too (XS = 1), while batched instances and the
+// pitched buffers of the adjoint keep plain rows (XS = 0).  pair_row(y) is the offset of
+// element (y, 0); the elements of a row then lie 2 apart.
+__device__ __forceinline__ size_t pair_row(int y, int ld) { return (size_t)(y >> 1) * 2 * ld + (y & 1); }
+template <int XS>
+__device__ __forceinline__ size_t x_row(int y, int ld) { return XS ? pair_row(y, ld) : (size_t)y * ld; }
 
 // Row kernels of one row per workgroup: blocks 16 q + j and 16 q + 8 + j (j < 8) take rows
 // 2 (8 q + j) and 2 (8 q + j) + 1, and dispatch sends both to the same XCD, whose L2 then
@@ -79,17 +83,18 @@ __device__ __forceinline__ void store_line(const V* d, double* __restrict__ v, i
     if (t + T * m < n) (v + T * m * st)[t * st] = d[m].x;
 }
 
-// Same pairs for a strided line (a grid column): each element is loaded once, the reversed
-// copy comes through LDS.
-template <int M, int E, int T, class L_t>
-__device__ __forceinline__ void load_column_pair(const L_t& L, V* d, const double* __restrict__ v, int st,
+// Same pairs for column `col` of an array with row pitch ld (paired rows when XS = 1): each
+// element is loaded once, the reversed copy comes through LDS.  T m is even, so slot m's
+// rows start at the uniform offset T m ld in both layouts.
+template <int M, int E, int T, int XS, class L_t>
+__device__ __forceinline__ void load_column_pair(const L_t& L, V* d, const double* __restrict__ X, int col, int ld,
                                                  void* lds, int n) {
   const int t = L.t;
   double a[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int k = t + T * m;
-    const double x = (v + T * m * st)[(min(k, n - 1) - T * m) * st];
+    const int k = t + T * m, kc = min(k, n - 1);
+    const double x = (X + T * m * ld)[((kc - T * m) >> XS) * (ld << XS) + (col << XS) + (kc & XS)];
     a[m] = k < n ? x : 0.0;
   }
   double* buf = reinterpret_cast<double*>(lds);
@@ -287,7 +292,7 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
 // rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M.
 // LF = 1 first completes the previous step's update: u = 2 u + (-uprev) + hat, with
 // u = ucur, hat = the increment left in X by the y-sweep; the result overwrites uprev.
-template <int M, int LF>
+template <int M, int LF, int XS>
 __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M,
                 int nrows) {
@@ -300,7 +305,7 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
   const int yy = live ? y : 0;
   const double* row = u + (size_t)yy * ldu;
   double* prow = LF ? uprev + (size_t)yy * ldu : nullptr;
-  const double* hrow = LF ? hat + (size_t)yy * ldx : nullptr;
+  const double* hrow = LF ? hat + x_row<XS>(yy, ldx) : nullptr;
   const int t = L.t;
   V d[E];
   // z[j] = x[2j] + i x[2j+1], j = t + T c, x[i] = 0 for i >= N (N <= M - 1): slots c >= E/2
@@ -314,8 +319,8 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
       double xe = (row + base)[ie];
       double xo = (row + base)[io];
       if constexpr (LF == 1) {
-        xe = 2.0 * xe - (prow + base)[ie] + (hrow + base)[ie];
-        xo = 2.0 * xo - (prow + base)[io] + (hrow + base)[io];
+        xe = 2.0 * xe - (prow + base)[ie] + (hrow + (base << XS))[ie << XS];
+        xo = 2.0 * xo - (prow + base)[io] + (hrow + (base << XS))[io << XS];
         if (live) {
           if (ve) (prow + base)[ie] = xe;
           if (vo) (prow + base)[io] = xo;
@@ -331,7 +336,7 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
   // pair Z[k] with Z[M-k] through a half-length complex buffer in two rounds: slots
   // m < E/2 hold k < M/2, the others k >= M/2; k = 0 and k = M/2 are their own partners.
   V* zb = reinterpret_cast<V*>(smem);
-  V* out = S + spec_row(live ? y : 0, lds_);   // element k at out[2 k]
+  V* out = S + pair_row(live ? y : 0, lds_);   // element k at out[2 k]
   auto emit = [&](int k, V zk, V zmk) {
     const V zm = cconj(zmk);
     const V ev = cscale(cadd(zk, zm), 0.5);
@@ -583,7 +588,7 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
   }
 }
 
-template <int M, int MODE>
+template <int M, int MODE, int XS>
 __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
@@ -596,18 +601,20 @@ __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int ld
   if (PAIRED && y >= n) return;   // a whole workgroup past the last row
   const bool live = y < n;
   const int yy = live ? y : 0;
-  double* xo = X + (size_t)yy * ldx;
   // MODE 3 / 4: as 0 / 1 but X = B (no line solve; the dense-inverse path follows)
   constexpr int RMODE = MODE >= 3 ? MODE - 3 : MODE;
+  static_assert(RMODE != 2 || XS == 0, "L_h output rows are plain");
   V d[E];
-  if (!rhs_phase<RMODE>(L, d, smem, S + spec_row(yy, lds_), u + (size_t)yy * ldu,
-                        RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n))
+  if (!rhs_phase<RMODE>(L, d, smem, S + pair_row(yy, lds_), u + (size_t)yy * ldu,
+                        RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, X + (size_t)yy * ldx, live, sc, tab,
+                        root2M, n))
     return;
   if constexpr (MODE < 3) gs_solve(L, d, smem, tab, gs, n);
   if (live) {
     // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
+    double* xo = X + x_row<XS>(yy, ldx);
 #pragma unroll
-    for (int m = 0; m < E; ++m) (xo + T * m)[L.t] = d[m].x;
+    for (int m = 0; m < E; ++m) (xo + ((T * m) << XS))[L.t << XS] = d[m].x;
   }
 }
 
@@ -629,7 +636,7 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   const int yy = live ? y : 0;
   double* xo = X + (size_t)yy * ldx;
   V d[E];
-  rhs_phase<MODE>(L, d, smem, S + spec_row(yy, lds_), u + (size_t)yy * ldu,
+  rhs_phase<MODE>(L, d, smem, S + pair_row(yy, lds_), u + (size_t)yy * ldu,
                   MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n);
   mixed_solve(L, Lf, d, smem, tab, mx);
   if (live) {
@@ -659,7 +666,7 @@ rows_gs_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTTables<
 // ----------------------------------------------------------------------------------
 // cols_gs: y-line solves on the columns of X and the leapfrog update.
 // MODE 0: uout = 2 ucur - uprev + Uhat (uout may alias uprev); MODE 1: uout = ucur + Uhat.
-template <int M, int MODE>
+template <int M, int MODE, int XS>
 __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* ucur, const double* uprev,
                double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
   using Cfg = ColGSCfg<M>;
@@ -674,13 +681,13 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
   const int cc = live ? col : 0;
   const int t = L.t;
   V d[E];
-  load_column_pair<M, E, T>(L, d, X + cc, ldx, smem, n);
+  load_column_pair<M, E, T, XS>(L, d, X, cc, ldx, smem, n);
   gs_solve(L, d, smem, tab, gs, n);
   if (!live) return;
   const int o = t * ldu + col;
   if constexpr (MODE == 2) {
     // the increment stays in X (the next row pass applies the update)
-    const int ox = t * ldx + col;
+    const int ox = (t >> XS) * (ldx << XS) + (col << XS) + (t & XS);
 #pragma unroll
     for (int m = 0; m < E; ++m)
       if (t + T * m < n) (X + T * m * ldx)[ox] = d[m].x;
@@ -763,13 +770,13 @@ template <int M, int LF>
 __global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
-  rows_fwd_body<M, LF>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M, n);
+  rows_fwd_body<M, LF, 1>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M, n);
 }
 template <int M, int LF>
 __global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_batched(const BatchInst* __restrict__ bi, int iu, int ip, int ldx, int lds_, int n, FFTTables<double> tab) {
   const BatchInst& p = bi[blockIdx.y];
-  rows_fwd_body<M, LF>(p.u[iu], p.u[ip], p.X, ldx, n, p.S, lds_, n, tab, tab.root2M, n);
+  rows_fwd_body<M, LF, 0>(p.u[iu], p.u[ip], p.X, ldx, n, p.S, lds_, n, tab, tab.root2M, n);
 }
 
 template <int M>
@@ -790,28 +797,28 @@ __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
-  rows_rhs_gs_body<M, MODE>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M);
+  rows_rhs_gs_body<M, MODE, (MODE < 2 ? 1 : 0)>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M);
 }
 template <int M, int MODE>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_batched(const BatchInst* __restrict__ bi, int iu, int lds_, int ldx, int n, FFTTables<double> tab) {
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
-  rows_rhs_gs_body<M, MODE>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M);
+  rows_rhs_gs_body<M, MODE, 0>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M);
 }
 
-template <int M, int MODE>
+template <int M, int MODE, int XS>
 __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_kernel(double* X, int ldx, const double* ucur, const double* uprev,
                double* uout, int ldu, int n, FFTTables<double> tab, GSTables64 gs, int ngroups) {
-  cols_gs_body<M, MODE>(X, ldx, ucur, uprev, uout, ldu, n, tab, gs, ngroups);
+  cols_gs_body<M, MODE, XS>(X, ldx, ucur, uprev, uout, ldu, n, tab, gs, ngroups);
 }
 template <int M>
 __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_batched(const BatchInst* __restrict__ bi, int ldx, int n, FFTTables<double> tab, int ngroups) {
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
-  cols_gs_body<M, 2>(p.X, ldx, nullptr, nullptr, nullptr, n, n, tab, gs, ngroups);
+  cols_gs_body<M, 2, 0>(p.X, ldx, nullptr, nullptr, nullptr, n, n, tab, gs, ngroups);
 }
 
 // batched update, instance blockIdx.z, row blockIdx.y:
@@ -950,7 +957,7 @@ template <int M>
 __global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_rect_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, int lds_, int nrows, int nlen,
                      FFTTables<double> tab) {
-  rows_fwd_body<M, 0>(u, nullptr, nullptr, 0, ldu, S, lds_, nlen, tab, tab.root2M, nrows);
+  rows_fwd_body<M, 0, 0>(u, nullptr, nullptr, 0, ldu, S, lds_, nlen, tab, tab.root2M, nrows);
 }
 
 // G(i, k) = 2 Re S[i][k] - a_i0 for i < n, k <= M, stored transposed: GT[k][i]
@@ -959,7 +966,7 @@ bccb_pass1_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ 
                   double* __restrict__ GT, int ldg) {
   const int k = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
   if (k > m) return;
-  GT[(size_t)k * ldg + i] = 2.0 * S[spec_row(i, lds_) + 2 * k].x - a2[i];
+  GT[(size_t)k * ldg + i] = 2.0 * S[pair_row(i, lds_) + 2 * k].x - a2[i];
 }
 
 // Lambda(kx, ky) = (2 Re T[ky][kx] - G(0, ky)) * scale, row kx of lam: even ky at ky/2, odd
@@ -970,7 +977,7 @@ bccb_pass2_kernel(const V* __restrict__ Tsp, int ldt, const double* __restrict__
   const int kx = blockIdx.x * 256 + threadIdx.x, ky = blockIdx.y;
   if (kx > m) return;
   const int pos = (ky % 2 == 0) ? ky / 2 : m / 2 + 1 + (ky - 1) / 2;
-  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[spec_row(ky, ldt) + 2 * kx].x - GT[(size_t)ky * ldg]) * scale;
+  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[pair_row(ky, ldt) + 2 * kx].x - GT[(size_t)ky * ldg]) * scale;
 }
 
 template <int M>
@@ -1011,7 +1018,7 @@ leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict_
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   if (i >= n) return;
   const size_t o = (size_t)j * n + i;
-  const double h = hat[(size_t)j * ldx + i];
+  const double h = hat[pair_row(j, ldx) + 2 * i];   // X in paired rows
   const double c = ucur[o];
   if (mode == 2) {           // newest into ucur, the current state into uprev
     const double v = 2.0 * c - uprev[o] + h;
@@ -1068,20 +1075,24 @@ void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<do
 }
 
 template <int M>
-void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
-                    int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st) {
+void launch_cols_gs(int mode, const double* X, int ldx, bool x_paired, const double* ucur, const double* uprev,
+                    double* uout, int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st) {
   const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
   const int grid = ((ngroups + 7) / 8) * 8;
   double* Xw = const_cast<double*>(X);
+  // modes 0 and 1 read the step's own X (paired rows); mode 2 also serves plain buffers
   if (mode == 0)
-    hipLaunchKernelGGL((cols_gs_kernel<M, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev, uout,
-                       ldu, n, tab, gs, ngroups);
+    hipLaunchKernelGGL((cols_gs_kernel<M, 0, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
+                       uout, ldu, n, tab, gs, ngroups);
   else if (mode == 1)
-    hipLaunchKernelGGL((cols_gs_kernel<M, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev, uout,
-                       ldu, n, tab, gs, ngroups);
+    hipLaunchKernelGGL((cols_gs_kernel<M, 1, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
+                       uout, ldu, n, tab, gs, ngroups);
+  else if (x_paired)
+    hipLaunchKernelGGL((cols_gs_kernel<M, 2, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
+                       uout, ldu, n, tab, gs, ngroups);
   else
-    hipLaunchKernelGGL((cols_gs_kernel<M, 2>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev, uout,
-                       ldu, n, tab, gs, ngroups);
+    hipLaunchKernelGGL((cols_gs_kernel<M, 2, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
+                       uout, ldu, n, tab, gs, ngroups);
 }
 
 template <int M>
@@ -1175,7 +1186,7 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
                                       hipStream_t);                                                              \
   template void launch_rows_gs<M>(double*, int, int, int, const FFTTables<double>&, const GSTables64&,            \
                                   hipStream_t);                                                                  \
-  template void launch_cols_gs<M>(int, const double*, int, const double*, const double*, double*, int, int,       \
+  template void launch_cols_gs<M>(int, const double*, int, bool, const double*, const double*, double*, int, int, \
                                   const FFTTables<double>&, const GSTables64&, hipStream_t);                     \
   template void launch_rows_rhs_mixed<M>(int, const V*, int, const double*, int, const double*, double*, int,     \
                                          int, const StepScalars&, const FFTTables<double>&, const MixedTables&,  \

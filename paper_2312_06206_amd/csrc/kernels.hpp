@@ -190,8 +190,8 @@ template <int M>
 void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab, const GSTables64& gs,
                     hipStream_t st);
 template <int M>
-void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
-                    int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
+void launch_cols_gs(int mode, const double* X, int ldx, bool x_paired, const double* ucur, const double* uprev,
+                    double* uout, int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
 // batched forms (instances in blockIdx.y; iu / ip select u[0] or u[1]).  Row pass modes:
 // 0 / 1 step / start-up with the x-sweep, 3 / 4 the same without it (X = B)
 template <int M>

@@ -79,12 +79,13 @@ template <int M> struct RowsRhs {
 };
 template <int M> struct ColsGS {
   static void run(const sadi_ctx* c, int mode, const double* ucur, const double* uprev, double* uout) {
-    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, ucur, uprev, uout, c->n, c->n, tables(c), gs_tables(c), c->stream);
+    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, true, ucur, uprev, uout, c->n, c->n, tables(c), gs_tables(c),
+                            c->stream);
   }
 };
 template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ldX buffer
   static void run(const sadi_ctx* c, double* buf) {
-    sadi::launch_cols_gs<M>(2, buf, c->ldX, nullptr, nullptr, nullptr, c->n, c->n, tables(c), gs_tables(c),
+    sadi::launch_cols_gs<M>(2, buf, c->ldX, false, nullptr, nullptr, nullptr, c->n, c->n, tables(c), gs_tables(c),
                             c->stream);
   }
 };
@@ -259,7 +260,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * lam_elems)) != SADI_OK) return bail(st);
   // rows stored in interleaved pairs: ceil(N / 2) pairs of 2 ldS complex values
   if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)(n + 1) * c->ldS)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)n * c->ldX)) != SADI_OK) return bail(st);
+  // X in paired rows: ceil(N / 2) pairs of 2 ldX values
+  if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)(n + 1) * c->ldX)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootM32, sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootS32, sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->q32, sizeof(float2) * m)) != SADI_OK) return bail(st);
