@@ -157,17 +157,18 @@ def adjoint_leg(seed: int) -> dict:
         a = to_dev(W.seeded_bump(n, seed))
         u_obs = s.first_step(a, torch.zeros_like(a))
         s.run(a, u_obs, steps - 1)
-    x = to_dev(W.seeded_bump(n, seed + 1)).requires_grad_(True)
-    k = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    uK = sadi_loop(x, k, alpha, n, tau, steps, checkpoint=50)
-    J = ((uK - u_obs) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    J.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    for _ in range(2):   # the first pass warms up; the second is timed (solver set-up included)
+        x = to_dev(W.seeded_bump(n, seed + 1)).requires_grad_(True)
+        k = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uK = sadi_loop(x, k, alpha, n, tau, steps, checkpoint=50)
+        J = ((uK - u_obs) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
     return {"workload": "N=511, alpha=1.6, 500 steps, tau=1e-3, loss ||u(T)-u_obs||^2, u_obs from kappa=1.3, "
                         "gradient w.r.t. kappa and phi1 at kappa=1, checkpoint every 50 steps",
             "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),

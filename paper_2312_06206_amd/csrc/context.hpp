@@ -2,6 +2,7 @@
 // batched entry points.  Not part of the C ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <cmath>
 #include <initializer_list>
@@ -53,8 +54,15 @@ struct sadi_ctx {
   int ldlam = 0;
   double2* S = nullptr;        // N rows x ldS complex
   int ldS = 0;
-  double* X = nullptr;         // N rows x ldX
+  double* X = nullptr;         // N rows x ldX (M rows when the correction is a GEMM)
   int ldX = 0;
+  // Large corrections (r > kTailGemmMinRank): the line solves leave the bordered solution of
+  // size M and one GEMM per sweep applies the rank-r correction to all lines.  X then keeps
+  // plain rows (the GEMM addresses it as a matrix); otherwise rows are paired.
+  static constexpr int kTailGemmMinRank = 32;
+  bool tail_gemm = false;
+  bool x_paired = true;
+  rocblas_handle blas = nullptr;   // created on first use
   // mixed precision: FP32 copies of the FFT and Gohberg-Semencul tables, FP64 eigenvalues
   // of the 2M-circulant embedding of beta T(a) (even / odd frequencies, scaled by 1/(2M))
   float2* rootM32 = nullptr;
@@ -86,6 +94,8 @@ struct sadi_ctx {
     return SADI_OK;
   }
   void release() {
+    if (blas) (void)rocblas_destroy_handle(blas);
+    blas = nullptr;
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -146,6 +156,10 @@ inline ShapeInfo shape_of(int m) {
 inline sadi::FFTTables<double> tables(const sadi_ctx* c) { return sadi::FFTTables<double>{c->rootM, c->rootS, c->root2M}; }
 inline sadi::GSTables64 gs_tables(const sadi_ctx* c) {
   return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f, c->r};
+}
+// tables of the time step's sweeps: r = 0 when the correction is left to the GEMM
+inline sadi::GSTables64 step_gs_tables(const sadi_ctx* c) {
+  return sadi::GSTables64{c->root2M, c->lam_s, c->lam_c, c->f, c->tail_gemm ? 0 : c->r};
 }
 
 

@@ -169,11 +169,13 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V2<typename LineT::Real
 #pragma unroll
   for (int m = 0; m < E; ++m) buf[wb + SC * T * m] = d[m].y;
   if (gs.r != 1) {
-    // N < M - 1: w for every slot, then w[N..M-1] through LDS, then the rank-r correction
+    // N < M - 1: w for every slot, then w[N..M-1] through LDS, then the rank-r correction.
+    // r = 0: stop at w (all M slots); the caller corrects all lines at once.
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) d[m].x += buf[rb + SC * T * (E - 1 - m)];
     __syncthreads();
+    if (gs.r == 0) return;
 #pragma unroll
     for (int m = 0; m < E; ++m)
       if (t + T * m >= n) buf[wb + SC * T * m] = d[m].x;
@@ -687,10 +689,12 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
   const int o = t * ldu + col;
   if constexpr (MODE == 2) {
     // the increment stays in X (the next row pass applies the update)
+    // with the correction deferred (r = 0) the bordered rows N..M-1 are kept as well
     const int ox = (t >> XS) * (ldx << XS) + (col << XS) + (t & XS);
+    const int nst = gs.r == 0 ? M : n;
 #pragma unroll
     for (int m = 0; m < E; ++m)
-      if (t + T * m < n) (X + T * m * ldx)[ox] = d[m].x;
+      if (t + T * m < nst) (X + T * m * ldx)[ox] = d[m].x;
   } else {
     // rows k = t + T m >= N: clamped loads, no store
     double uc[E], up[E];
@@ -766,11 +770,11 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
 // ----------------------------------------------------------------------------------
 // kernels: one instance (pointer arguments) and batched (instance blockIdx.y of an
 // array of BatchInst sharing N, pitches and line tables; iu / ip pick the state buffers)
-template <int M, int LF>
+template <int M, int LF, int XS>
 __global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
 rows_fwd_kernel(const double* __restrict__ u, double* __restrict__ uprev, const double* __restrict__ hat, int ldx,
                 int ldu, V* __restrict__ S, int lds_, int n, FFTTables<double> tab, const V* __restrict__ root2M) {
-  rows_fwd_body<M, LF, 1>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M, n);
+  rows_fwd_body<M, LF, XS>(u, uprev, hat, ldx, ldu, S, lds_, n, tab, root2M, n);
 }
 template <int M, int LF>
 __global__ void __launch_bounds__(RowFwdCfg<M>::NT) SADI_OCC4
@@ -792,12 +796,12 @@ cols_conv_batched(const BatchInst* __restrict__ bi, int lds_, int n, int ldlam, 
   cols_conv_body<M>(p.S, lds_, n, p.lam2d, ldlam, tab, tab.root2M, ngroups);
 }
 
-template <int M, int MODE>
+template <int M, int MODE, int XS>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
-  rows_rhs_gs_body<M, MODE, (MODE < 2 ? 1 : 0)>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M);
+  rows_rhs_gs_body<M, MODE, XS>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M);
 }
 template <int M, int MODE>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
@@ -999,26 +1003,30 @@ void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg
 // ----------------------------------------------------------------------------------
 // host-side launchers
 template <int M>
-void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, V* S, int lds_, int n,
-                     const FFTTables<double>& tab, const V* root2M, hipStream_t st) {
+void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, bool x_paired, int ldu, V* S,
+                     int lds_, int n, const FFTTables<double>& tab, const V* root2M, hipStream_t st) {
   const int grid = (n + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW;
+  const dim3 blk(RowFwdCfg<M>::NT);
   if (hat == nullptr)
-    hipLaunchKernelGGL((rows_fwd_kernel<M, 0>), dim3(grid), dim3(RowFwdCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu,
-                       S, lds_, n, tab, root2M);
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 0, 0>), dim3(grid), blk, 0, st, u, uprev, hat, ldx, ldu, S, lds_, n, tab,
+                       root2M);
+  else if (x_paired)
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 1, 1>), dim3(grid), blk, 0, st, u, uprev, hat, ldx, ldu, S, lds_, n, tab,
+                       root2M);
   else
-    hipLaunchKernelGGL((rows_fwd_kernel<M, 1>), dim3(grid), dim3(RowFwdCfg<M>::NT), 0, st, u, uprev, hat, ldx, ldu,
-                       S, lds_, n, tab, root2M);
+    hipLaunchKernelGGL((rows_fwd_kernel<M, 1, 0>), dim3(grid), blk, 0, st, u, uprev, hat, ldx, ldu, S, lds_, n, tab,
+                       root2M);
 }
 
 // out = 2 ucur - uprev + hat (mode 0, out may alias uprev), out = ucur + hat (mode 1), or
 // (ucur, uprev) <- (2 ucur - uprev + hat, ucur) (mode 2)
 __global__ void __launch_bounds__(256)
-leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict__ hat, int ldx, double* out,
-                int n) {
+leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict__ hat, int ldx, int xs,
+                double* out, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   if (i >= n) return;
   const size_t o = (size_t)j * n + i;
-  const double h = hat[pair_row(j, ldx) + 2 * i];   // X in paired rows
+  const double h = hat[xs ? pair_row(j, ldx) + 2 * i : (size_t)j * ldx + i];   // xs: X in paired rows
   const double c = ucur[o];
   if (mode == 2) {           // newest into ucur, the current state into uprev
     const double v = 2.0 * c - uprev[o] + h;
@@ -1029,9 +1037,10 @@ leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict_
   }
 }
 
-void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, double* out, int n,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(leapfrog_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, mode, ucur, uprev, hat, ldx, out, n);
+void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, bool x_paired, double* out,
+                     int n, hipStream_t st) {
+  hipLaunchKernelGGL(leapfrog_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, mode, ucur, uprev, hat, ldx,
+                     x_paired ? 1 : 0, out, n);
 }
 
 template <int M>
@@ -1053,18 +1062,26 @@ int rhs_grid(int n) {
 
 template <int M>
 void launch_rows_rhs_gs(int mode, const V* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
-                        int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const GSTables64& gs,
-                        const V* root2M, hipStream_t st) {
+                        int ldx, bool x_paired, int n, const StepScalars& sc, const FFTTables<double>& tab,
+                        const GSTables64& gs, const V* root2M, hipStream_t st) {
   const int grid = rhs_grid<M>(n);
-  if (mode == 0)
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
-                       ldx, n, sc, tab, gs, root2M);
+  const dim3 blk(RowCfg<M>::NT);
+  // mode 2 (L_h only) writes plain rows
+  if (mode == 0 && x_paired)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 1>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+                       tab, gs, root2M);
+  else if (mode == 0)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+                       tab, gs, root2M);
+  else if (mode == 1 && x_paired)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1, 1>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+                       tab, gs, root2M);
   else if (mode == 1)
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
-                       ldx, n, sc, tab, gs, root2M);
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+                       tab, gs, root2M);
   else
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 2>), dim3(grid), dim3(RowCfg<M>::NT), 0, st, S, lds_, u, ldu, phi2, X,
-                       ldx, n, sc, tab, gs, root2M);
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 2, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+                       tab, gs, root2M);
 }
 
 template <int M>
@@ -1177,13 +1194,13 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
 }
 
 #define SADI_INSTANTIATE(M)                                                                                      \
-  template void launch_rows_fwd<M>(const double*, double*, const double*, int, int, V*, int, int,              \
+  template void launch_rows_fwd<M>(const double*, double*, const double*, int, bool, int, V*, int, int,        \
                                    const FFTTables<double>&, const V*, hipStream_t);                             \
   template void launch_cols_conv<M>(V*, int, int, const double*, int, const FFTTables<double>&, const V*,        \
                                     hipStream_t);                                                                \
-  template void launch_rows_rhs_gs<M>(int, const V*, int, const double*, int, const double*, double*, int, int,   \
-                                      const StepScalars&, const FFTTables<double>&, const GSTables64&, const V*,  \
-                                      hipStream_t);                                                              \
+  template void launch_rows_rhs_gs<M>(int, const V*, int, const double*, int, const double*, double*, int, bool, \
+                                      int, const StepScalars&, const FFTTables<double>&, const GSTables64&,       \
+                                      const V*, hipStream_t);                                                    \
   template void launch_rows_gs<M>(double*, int, int, int, const FFTTables<double>&, const GSTables64&,            \
                                   hipStream_t);                                                                  \
   template void launch_cols_gs<M>(int, const double*, int, bool, const double*, const double*, double*, int, int, \

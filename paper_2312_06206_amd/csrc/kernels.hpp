@@ -15,7 +15,7 @@ template <typename R> struct GSTables {
   const V2<R>* lam_s;    // fft(Q s) / (2 p_1 M)
   const V2<R>* lam_c;    // fft(c) / M
   const R* f;            // correction to H_N^-1: r = 1: (J c)[k] / p_1, k < N; else F, r rows of N
-  int r;                 // M - N
+  int r;                 // M - N; 0: no correction (the bordered solution of size M is left)
 };
 using GSTables64 = GSTables<double>;
 
@@ -173,19 +173,20 @@ struct BatchInst {
   StepScalars sc;           // sigma, gamma carry this instance's kappa, h^-alpha, tau
 };
 
-// hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev)
+// hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev);
+// x_paired: hat (pitch ldx) in paired rows, else plain rows
 template <int M>
-void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, double2* S, int lds_,
-                     int n, const FFTTables<double>& tab, const double2* root2M, hipStream_t st);
-void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, double* out, int n,
-                     hipStream_t st);
+void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, bool x_paired, int ldu,
+                     double2* S, int lds_, int n, const FFTTables<double>& tab, const double2* root2M, hipStream_t st);
+void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, bool x_paired, double* out,
+                     int n, hipStream_t st);
 template <int M>
 void launch_cols_conv(double2* S, int lds_, int n, const double* lam, int ldlam, const FFTTables<double>& tab,
                       const double2* root2M, hipStream_t st);
 template <int M>
 void launch_rows_rhs_gs(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
-                        int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const GSTables64& gs,
-                        const double2* root2M, hipStream_t st);
+                        int ldx, bool x_paired, int n, const StepScalars& sc, const FFTTables<double>& tab,
+                        const GSTables64& gs, const double2* root2M, hipStream_t st);
 template <int M>
 void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab, const GSTables64& gs,
                     hipStream_t st);

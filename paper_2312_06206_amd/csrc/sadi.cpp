@@ -61,8 +61,8 @@ namespace {
 
 template <int M> struct RowsFwd {
   static void run(const sadi_ctx* c, const double* u, double* lf_prev) {
-    sadi::launch_rows_fwd<M>(u, lf_prev, lf_prev ? c->X : nullptr, c->ldX, c->n, c->S, c->ldS, c->n, tables(c),
-                             c->root2M, c->stream);
+    sadi::launch_rows_fwd<M>(u, lf_prev, lf_prev ? c->X : nullptr, c->ldX, c->x_paired, c->n, c->S, c->ldS, c->n,
+                             tables(c), c->root2M, c->stream);
   }
 };
 template <int M> struct ColsConv {
@@ -73,14 +73,14 @@ template <int M> struct ColsConv {
 template <int M> struct RowsRhs {
   static void run(const sadi_ctx* c, int mode, const double* u, const double* phi2, double* X, int ldx,
                   const sadi::StepScalars& sc) {
-    sadi::launch_rows_rhs_gs<M>(mode, c->S, c->ldS, u, c->n, phi2, X, ldx, c->n, sc, tables(c), gs_tables(c),
-                                c->root2M, c->stream);
+    sadi::launch_rows_rhs_gs<M>(mode, c->S, c->ldS, u, c->n, phi2, X, ldx, c->x_paired, c->n, sc, tables(c),
+                                step_gs_tables(c), c->root2M, c->stream);
   }
 };
 template <int M> struct ColsGS {
   static void run(const sadi_ctx* c, int mode, const double* ucur, const double* uprev, double* uout) {
-    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, true, ucur, uprev, uout, c->n, c->n, tables(c), gs_tables(c),
-                            c->stream);
+    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, c->x_paired, ucur, uprev, uout, c->n, c->n, tables(c),
+                            step_gs_tables(c), c->stream);
   }
 };
 template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ldX buffer
@@ -91,7 +91,8 @@ template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ld
 };
 template <int M> struct RowsFwdPitched {  // spectrum of a grid function with row pitch ld
   static void run(const sadi_ctx* c, const double* u, int ld) {
-    sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, ld, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
+    sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, false, ld, c->S, c->ldS, c->n, tables(c), c->root2M,
+                             c->stream);
   }
 };
 template <int M> struct BccbEig {
@@ -132,6 +133,33 @@ template <int M> struct RowsGSMixed {
   }
 };
 
+// Rank-r correction of every line of X from its bordered solution w (size M, the step's
+// sweeps ran with r = 0): x = w[0:N] - F w[N:M] with F stored as r rows of N (section
+// "Fast implementation based on GS formula" solves at size M; the Schur complement of the
+// bordered matrix gives H_N^-1).  rows: X[y][k] -= sum_j X[y][N+j] F[j][k]; columns:
+// X[k][c] -= sum_j F[j][k] X[N+j][c].  In column-major terms X^T is M x N (pitch ldX) and
+// G = F^T is N x r (pitch N).
+sadi_status tail_correct(sadi_ctx* c, bool columns) {
+  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return fail(SADI_E_DEVICE, "rocblas_create_handle");
+  }
+  rocblas_status st = rocblas_set_stream(c->blas, c->stream);
+  const double minus_one = -1.0, one = 1.0;
+  const int n = c->n, r = c->r, ld = c->ldX;
+  if (st == rocblas_status_success) {
+    if (!columns)   // (X^T)[0:N, :] -= G (X^T)[N:M, :]
+      st = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, n, r, &minus_one, c->f, n,
+                         c->X + n, ld, &one, c->X, ld);
+    else            // (X^T)[:, 0:N] -= (X^T)[:, N:M] G^T
+      st = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, n, n, r, &minus_one,
+                         c->X + (size_t)n * ld, ld, c->f, n, &one, c->X, ld);
+  }
+  if (st != rocblas_status_success)
+    return fail(SADI_E_DEVICE, std::string("rocblas_dgemm: ") + rocblas_status_to_string(st));
+  return SADI_OK;
+}
+
 // one step of the delta form on the device; mode 0: uout = 2 ucur - uprev + Uhat,
 // mode 1 (start-up): uout = ucur + Uhat with phi2.
 // Deferred update (FP64 runs): cols_mode 2 leaves Uhat in X instead of forming uout, and a
@@ -151,14 +179,27 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
   dispatch_m<ColsConv>(c->m, c);
   mark(2);
   const sadi::StepScalars sc = scalars(c, mode == 1);
-  if (c->prec == SADI_FP64)
+  if (c->prec == SADI_FP64) {
     dispatch_m<RowsRhs>(c->m, c, mode, ucur, phi2, c->X, c->ldX, sc);
-  else
+    if (c->tail_gemm) {
+      sadi_status st = tail_correct(c, false);
+      if (st != SADI_OK) return st;
+    }
+  } else {
     dispatch_m<RowsRhsMixed>(c->m, c, mode, ucur, phi2, sc);
+  }
   mark(3);
-  if (c->prec == SADI_FP64)
+  if (c->prec == SADI_FP64 && c->tail_gemm) {
+    // Uhat into X, its correction, then the update unless the next row pass applies it
+    dispatch_m<ColsGS>(c->m, c, 2, ucur, uprev, uout);
+    sadi_status st = tail_correct(c, true);
+    if (st != SADI_OK) return st;
+    if (cols_mode != 2)
+      sadi::launch_leapfrog(cols_mode == 0 ? 0 : 1, const_cast<double*>(ucur), const_cast<double*>(uprev), c->X,
+                            c->ldX, c->x_paired, uout, c->n, c->stream);
+  } else if (c->prec == SADI_FP64) {
     dispatch_m<ColsGS>(c->m, c, cols_mode, ucur, uprev, uout);
-  else
+  } else
     dispatch_m<ColsGSMixed>(c->m, c, mode, ucur, uprev, uout);
   mark(4);
   if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
@@ -172,6 +213,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   c->n = n;
   c->m = sadi::line_size(n);
   c->r = c->m - n;
+  c->tail_gemm = c->r > sadi_ctx::kTailGemmMinRank;
+  c->x_paired = !c->tail_gemm;
   c->alpha = alpha;
   c->kappa = kappa;
   c->tau = tau;
@@ -260,8 +303,10 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * lam_elems)) != SADI_OK) return bail(st);
   // rows stored in interleaved pairs: ceil(N / 2) pairs of 2 ldS complex values
   if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)(n + 1) * c->ldS)) != SADI_OK) return bail(st);
-  // X in paired rows: ceil(N / 2) pairs of 2 ldX values
-  if ((st = c->alloc((void**)&c->X, sizeof(double) * (size_t)(n + 1) * c->ldX)) != SADI_OK) return bail(st);
+  // X: N rows (paired rows: ceil(N / 2) pairs of 2 ldX values), or the M rows of the bordered
+  // y-line solutions when the correction is a GEMM
+  const size_t xrows = c->tail_gemm ? (size_t)m : (size_t)n + 1;
+  if ((st = c->alloc((void**)&c->X, sizeof(double) * xrows * c->ldX)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootM32, sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->rootS32, sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
   if ((st = c->alloc((void**)&c->q32, sizeof(float2) * m)) != SADI_OK) return bail(st);
@@ -419,9 +464,9 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
     }
     // the pending update leaves the newest state in u_cur and the one before in u_prev
     if (b == u_cur)
-      sadi::launch_leapfrog(2, b, a, c->X, c->ldX, nullptr, c->n, c->stream);
+      sadi::launch_leapfrog(2, b, a, c->X, c->ldX, c->x_paired, nullptr, c->n, c->stream);
     else
-      sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
+      sadi::launch_leapfrog(0, b, a, c->X, c->ldX, c->x_paired, a, c->n, c->stream);
     return check_launch();
   }
   for (int s = 0; s < nsteps; ++s) {
