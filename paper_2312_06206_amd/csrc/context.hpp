@@ -21,6 +21,9 @@ bool finite_all(std::initializer_list<double> v);
 bool supported_n(int n);
 // host threads for the set-up maths of the calling thread (0: all hardware threads)
 extern thread_local int g_setup_threads;
+// whether set-up prepares the GEMM of large corrections (rocBLAS handle and a first call)
+// for the single-instance time step; batch members never take that path
+extern thread_local bool g_setup_step_gemm;
 // argument checks of sadi_setup (allow2: alpha = 2 accepted, for injected tables)
 sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2);
 }  // namespace sadi_impl
@@ -62,7 +65,7 @@ struct sadi_ctx {
   static constexpr int kTailGemmMinRank = 32;
   bool tail_gemm = false;
   bool x_paired = true;
-  rocblas_handle blas = nullptr;   // created on first use
+  rocblas_handle blas = nullptr;   // created at set-up (single instances)
   // mixed precision: FP32 copies of the FFT and Gohberg-Semencul tables, FP64 eigenvalues
   // of the 2M-circulant embedding of beta T(a) (even / odd frequencies, scaled by 1/(2M))
   float2* rootM32 = nullptr;

@@ -19,6 +19,7 @@ namespace sadi_impl {
 
 thread_local std::string g_last_error;
 thread_local int g_setup_threads = 0;
+thread_local bool g_setup_step_gemm = true;
 
 sadi_status fail(sadi_status st, const std::string& msg) {
   g_last_error = msg;
@@ -368,6 +369,14 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     drop();
     if (e != hipSuccess) return bail(fail(SADI_E_DEVICE, std::string("eigenvalue set-up: ") + hipGetErrorString(e)));
+  }
+  // ---- large corrections: the rocBLAS handle and one call of each GEMM now, so that the
+  // time step itself allocates nothing
+  if (c->tail_gemm && g_setup_step_gemm) {
+    if (hipMemsetAsync(c->X, 0, sizeof(double) * (size_t)m * c->ldX, c->stream) != hipSuccess)
+      return bail(fail(SADI_E_DEVICE, "hipMemsetAsync"));
+    if ((st = tail_correct(c, false)) != SADI_OK || (st = tail_correct(c, true)) != SADI_OK) return bail(st);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(SADI_E_DEVICE, "correction set-up"));
   }
   *out = c;
   return SADI_OK;
