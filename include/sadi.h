@@ -126,10 +126,12 @@ sadi_status sadi_apply_lh(sadi_ctx* ctx, const double* u, double* out);
  * step (one event before the first kernel and one after each kernel), so each
  * kernel's device time is the difference of consecutive events.  Enabling resets
  * the accumulators; events are created on demand (at most 8192 steps are kept).
- * sadi_get_kernel_times synchronises the stream and writes, for the four kernels
+ * sadi_get_kernel_times synchronises the stream and writes, for the four parts
  * of a step -- 0 row forward transforms, 1 column convolution, 2 row inverse
  * transforms + right-hand side + x-line solves, 3 y-line solves + update --
- * the summed milliseconds (ms[4]) and the number of launches timed (count[4]). */
+ * the summed milliseconds (ms[4]) and the number of steps timed (count[4]).  In a
+ * float64 sadi_run the y-line kernel also does the next step's row transforms (on the
+ * transposed grid), so part 0 holds time only for the run's first step. */
 sadi_status sadi_set_kernel_timing(sadi_ctx* ctx, int enable);
 sadi_status sadi_get_kernel_times(sadi_ctx* ctx, double* ms, long long* count);
 

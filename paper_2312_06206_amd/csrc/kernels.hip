@@ -290,6 +290,56 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
   (void)M;
 }
 
+// Half spectrum of a real line of length P = 2M (zero beyond N) from its packed form:
+// on entry slot c holds z[j] = x[2j] + i x[2j+1], j = t + T c.  One complex transform of
+// length M, then X[k] = FE[k] + W_P^k FO[k] for k = 0..M, stored to out[2 k] (a row of the
+// paired-row spectrum) when `live`.
+template <class L_t>
+__device__ __forceinline__ void real_transform_store(const L_t& L, V* d, void* smem, V* __restrict__ out, bool live,
+                                                     const FFTTables<double>& tab, const V* __restrict__ root2M) {
+  constexpr int M = L_t::M, E = L_t::E, T = L_t::T;
+  L.template transform<-1>(d, smem, tab);
+  // pair Z[k] with Z[M-k] through a half-length complex buffer in two rounds: slots
+  // m < E/2 hold k < M/2, the others k >= M/2; k = 0 and k = M/2 are their own partners.
+  V* zb = reinterpret_cast<V*>(smem);
+  auto emit = [&](int k, V zk, V zmk) {
+    const V zm = cconj(zmk);
+    const V ev = cscale(cadd(zk, zm), 0.5);
+    const V od = cscale(csub(zk, zm), 0.5);        // = i * FO[k]
+    const V fo = V{od.y, -od.x};                   // X[k] = FE[k] + W_P^k FO[k]
+    if (live) out[2 * k] = cadd(ev, cmul(fo, root2M[k]));
+  };
+#pragma unroll
+  for (int round = 0; round < 2; ++round) {
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      const bool lower = c < E / 2;
+      if (lower == (round == 0)) {
+        const int k = L.t + T * c;
+        zb[L.cidx(lower ? k : k - M / 2)] = d[c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      const bool lower = c < E / 2;
+      const int k = L.t + T * c;
+      if (lower != (round == 0)) {
+        if (k == 0) {
+          emit(0, d[c], d[c]);
+          if (live) out[2 * M] = V{d[c].x - d[c].y, 0.0};   // X[M] = Re Z0 - Im Z0
+        } else if (k == M / 2) {
+          emit(k, d[c], d[c]);
+        } else {
+          const int km = M - k;
+          emit(k, d[c], zb[L.cidx(lower ? km - M / 2 : km)]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------------------------
 // rows_fwd: S[y][k] = sum_{n<N} u[y][n] e^{-2 pi i k n / P}, k = 0..M.
 // LF = 1 first completes the previous step's update: u = 2 u + (-uprev) + hat, with
@@ -334,47 +384,7 @@ __device__ __forceinline__ void rows_fwd_body(const double* __restrict__ u, doub
       d[c] = V{0.0, 0.0};
     }
   }
-  L.template transform<-1>(d, smem, tab);
-  // pair Z[k] with Z[M-k] through a half-length complex buffer in two rounds: slots
-  // m < E/2 hold k < M/2, the others k >= M/2; k = 0 and k = M/2 are their own partners.
-  V* zb = reinterpret_cast<V*>(smem);
-  V* out = S + pair_row(live ? y : 0, lds_);   // element k at out[2 k]
-  auto emit = [&](int k, V zk, V zmk) {
-    const V zm = cconj(zmk);
-    const V ev = cscale(cadd(zk, zm), 0.5);
-    const V od = cscale(csub(zk, zm), 0.5);        // = i * FO[k]
-    const V fo = V{od.y, -od.x};                   // X[k] = FE[k] + W_P^k FO[k]
-    if (live) out[2 * k] = cadd(ev, cmul(fo, root2M[k]));
-  };
-#pragma unroll
-  for (int round = 0; round < 2; ++round) {
-#pragma unroll
-    for (int c = 0; c < E; ++c) {
-      const bool lower = c < E / 2;
-      if (lower == (round == 0)) {
-        const int k = L.t + T * c;
-        zb[L.cidx(lower ? k : k - M / 2)] = d[c];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < E; ++c) {
-      const bool lower = c < E / 2;
-      const int k = L.t + T * c;
-      if (lower != (round == 0)) {
-        if (k == 0) {
-          emit(0, d[c], d[c]);
-          if (live) out[2 * M] = V{d[c].x - d[c].y, 0.0};   // X[M] = Re Z0 - Im Z0
-        } else if (k == M / 2) {
-          emit(k, d[c], d[c]);
-        } else {
-          const int km = M - k;
-          emit(k, d[c], zb[L.cidx(lower ? km - M / 2 : km)]);
-        }
-      }
-    }
-    __syncthreads();
-  }
+  real_transform_store(L, d, smem, S + pair_row(live ? y : 0, lds_), live, tab, root2M);
 }
 
 // f(integral_constant<int, C>) for every slot C, in order
@@ -613,10 +623,13 @@ __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int ld
     return;
   if constexpr (MODE < 3) gs_solve(L, d, smem, tab, gs, n);
   if (live) {
-    // X rows have M >= N + 1 slots: the value at k = N lands in the row padding
+    // X rows have M >= N + 1 slots: the value at k = N lands in the row padding.  The lane
+    // offset is recomputed from an opaque copy of the lane index (register pressure).
     double* xo = X + x_row<XS>(yy, ldx);
+    int tt = L.t;
+    asm volatile("" : "+v"(tt));
 #pragma unroll
-    for (int m = 0; m < E; ++m) (xo + ((T * m) << XS))[L.t << XS] = d[m].x;
+    for (int m = 0; m < E; ++m) (xo + ((T * m) << XS))[tt << XS] = d[m].x;
   }
 }
 
@@ -686,30 +699,163 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
   load_column_pair<M, E, T, XS>(L, d, X, cc, ldx, smem, n);
   gs_solve(L, d, smem, tab, gs, n);
   if (!live) return;
-  const int o = t * ldu + col;
+  // row offsets below come from an opaque copy of the lane index, so they are not kept
+  // live across the solve from the column load (register pressure)
+  int tt = t;
+  asm volatile("" : "+v"(tt));
+  const int o = tt * ldu + col;
   if constexpr (MODE == 2) {
     // the increment stays in X (the next row pass applies the update)
     // with the correction deferred (r = 0) the bordered rows N..M-1 are kept as well
-    const int ox = (t >> XS) * (ldx << XS) + (col << XS) + (t & XS);
+    const int ox = (tt >> XS) * (ldx << XS) + (col << XS) + (tt & XS);
     const int nst = gs.r == 0 ? M : n;
 #pragma unroll
     for (int m = 0; m < E; ++m)
-      if (t + T * m < nst) (X + T * m * ldx)[ox] = d[m].x;
+      if (tt + T * m < nst) (X + T * m * ldx)[ox] = d[m].x;
   } else {
     // rows k = t + T m >= N: clamped loads, no store
     double uc[E], up[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int oc = (min(t + T * m, n - 1) - T * m) * ldu + col;
+      const int oc = (min(tt + T * m, n - 1) - T * m) * ldu + col;
       uc[m] = (ucur + T * m * ldu)[oc];
       if constexpr (MODE == 0) up[m] = (uprev + T * m * ldu)[oc];
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if (t + T * m < n) {
+      if (tt + T * m < n) {
         if constexpr (MODE == 0) (uout + T * m * ldu)[o] = 2.0 * uc[m] - up[m] + d[m].x;
         else (uout + T * m * ldu)[o] = uc[m] + d[m].x;
       }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// cols_gs_fwd: one kernel for the end of a step and the start of the next, with the grid
+// transposed from one step to the next.  The scheme is symmetric in x and y (square grid,
+// one line matrix H, Lambda symmetric in (kx, ky), g pointwise), so a step on the
+// transposed state gives the transposed result.  For column c of this step's grid:
+//   Uhat = y-line solve of column c of X (paired rows),
+//   u^{n+1}[k][c] = 2 u^n[k][c] - u^{n-1}[k][c] + Uhat[k],
+// with ucur = u^n in this step's layout (column c read with stride N) and prev_t =
+// u^{n-1} in the transposed layout (its row c is column c here, contiguous).  The new
+// column is stored as row c of prev_t: u^{n+1} in the transposed layout, the layout of the
+// next step.  With `fwd` the same column is then transformed along its length, which is
+// the next step's row transform: its half spectrum goes to row c of S.
+template <int M>
+__device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
+                                                 double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_,
+                                                 FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M,
+                                                 int ngroups, int fwd) {
+  using Cfg = ColGSCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;   // whole workgroup
+  const L_t L(threadIdx.x);
+  const int col = grp * Cfg::LPW + L.line;
+  const bool live = col < n;
+  const int cc = live ? col : 0;
+  const int t = L.t;
+  V d[E];
+  load_column_pair<M, E, T, 1>(L, d, X, cc, ldx, smem, n);
+  gs_solve(L, d, smem, tab, gs, n);
+  // an opaque copy of the lane index: the row indices below are recomputed rather than
+  // kept live across the solve from the column load (register pressure)
+  int tt = t;
+  asm volatile("" : "+v"(tt));
+  // k = t + T m; rows k >= N are outside the grid (clamped loads, zero values).  Each new
+  // value goes straight to memory and, for the transform, to LDS (the solve has finished
+  // its LDS reads).
+  const double* uc = ucur + cc;
+  double* up = prev_t + (size_t)cc * n;
+  double* buf = reinterpret_cast<double*>(smem);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = tt + T * m, kc = min(k, n - 1);
+    // uniform base of slot m plus a 32-bit lane offset (negative only for clamped rows)
+    const double a = (uc + (size_t)T * m * n)[(kc - T * m) * n];
+    const double b = (up + T * m)[kc - T * m];
+    const double v = k < n ? 2.0 * a - b + d[m].x : 0.0;
+    if (live && k < n) (up + T * m)[tt] = v;
+    if (fwd) L.put_real(buf, k, v);
+  }
+  if (!fwd) return;   // uniform
+  // z[j] = x[2j] + i x[2j+1], j = t + T c (c < E/2; the other slots are zero)
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    if (c < E / 2) {
+      const int j = t + T * c;
+      d[c] = V{L.get_real(buf, 2 * j), L.get_real(buf, 2 * j + 1)};
+    } else {
+      d[c] = V{0.0, 0.0};
+    }
+  }
+  __syncthreads();
+  real_transform_store(L, d, smem, S + pair_row(cc, lds_), live, tab, root2M);
+}
+
+// ----------------------------------------------------------------------------------
+// Square N x N transposes in 32 x 32 tiles; block (I, J) with I <= J handles the tile pair
+// {(I, J), (J, I)} (blocks with I > J exit).  transpose_inplace: A <- A^T.  swap_transposed:
+// (cur, prev) <- (prev^T, cur).
+__global__ void __launch_bounds__(256) transpose_inplace_kernel(double* A, int n) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ double ta[32][33], tb[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int ra = I * 32 + r, ca = J * 32 + tx;   // tile (I, J)
+    const int rb = J * 32 + r, cb = I * 32 + tx;   // tile (J, I)
+    ta[r][tx] = (ra < n && ca < n) ? A[(size_t)ra * n + ca] : 0.0;
+    tb[r][tx] = (rb < n && cb < n) ? A[(size_t)rb * n + cb] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int ra = I * 32 + r, ca = J * 32 + tx;   // (I, J) <- (J, I)^T
+    const int rb = J * 32 + r, cb = I * 32 + tx;   // (J, I) <- (I, J)^T
+    if (ra < n && ca < n) A[(size_t)ra * n + ca] = tb[tx][r];
+    if (I != J && rb < n && cb < n) A[(size_t)rb * n + cb] = ta[tx][r];
+  }
+}
+
+__global__ void __launch_bounds__(256) swap_transposed_kernel(double* cur, double* prev, int n) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ double ta[32][33], tb[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  double ca_v[4], cb_v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int ra = I * 32 + r, ca = J * 32 + tx;
+    const int rb = J * 32 + r, cb = I * 32 + tx;
+    const bool ia = ra < n && ca < n, ib = rb < n && cb < n;
+    ta[r][tx] = ia ? prev[(size_t)ra * n + ca] : 0.0;
+    tb[r][tx] = ib ? prev[(size_t)rb * n + cb] : 0.0;
+    ca_v[q] = ia ? cur[(size_t)ra * n + ca] : 0.0;
+    cb_v[q] = ib ? cur[(size_t)rb * n + cb] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int ra = I * 32 + r, ca = J * 32 + tx;
+    const int rb = J * 32 + r, cb = I * 32 + tx;
+    if (ra < n && ca < n) {
+      cur[(size_t)ra * n + ca] = tb[tx][r];
+      prev[(size_t)ra * n + ca] = ca_v[q];
+    }
+    if (I != J && rb < n && cb < n) {
+      cur[(size_t)rb * n + cb] = ta[tx][r];
+      prev[(size_t)rb * n + cb] = cb_v[q];
     }
   }
 }
@@ -823,6 +969,14 @@ cols_gs_batched(const BatchInst* __restrict__ bi, int ldx, int n, FFTTables<doub
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
   cols_gs_body<M, 2, 0>(p.X, ldx, nullptr, nullptr, nullptr, n, n, tab, gs, ngroups);
+}
+
+template <int M>
+__global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
+cols_gs_fwd_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur, double* __restrict__ prev_t,
+                   int n, V* __restrict__ S, int lds_, FFTTables<double> tab, GSTables64 gs,
+                   const V* __restrict__ root2M, int ngroups, int fwd) {
+  cols_gs_fwd_body<M>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, ngroups, fwd);
 }
 
 // batched update, instance blockIdx.z, row blockIdx.y:
@@ -1134,6 +1288,25 @@ void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTab
 }
 
 template <int M>
+void launch_cols_gs_fwd(const double* X, int ldx, const double* ucur, double* prev_t, int n, V* S, int lds_, bool fwd,
+                        const FFTTables<double>& tab, const GSTables64& gs, const V* root2M, hipStream_t st) {
+  const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
+  const int grid = ((ngroups + 7) / 8) * 8;
+  hipLaunchKernelGGL(cols_gs_fwd_kernel<M>, dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n, S,
+                     lds_, tab, gs, root2M, ngroups, fwd ? 1 : 0);
+}
+
+void launch_transpose_inplace(double* A, int n, hipStream_t st) {
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(transpose_inplace_kernel, dim3(nt, nt), dim3(256), 0, st, A, n);
+}
+
+void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st) {
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(swap_transposed_kernel, dim3(nt, nt), dim3(256), 0, st, cur, prev, n);
+}
+
+template <int M>
 void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                           int ldu, int n, const FFTTables<double>& tab, const MixedTables& mx, hipStream_t st) {
   const int ngroups = (n + MixColCfg<M>::LPW - 1) / MixColCfg<M>::LPW;
@@ -1205,6 +1378,8 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
                                   hipStream_t);                                                                  \
   template void launch_cols_gs<M>(int, const double*, int, bool, const double*, const double*, double*, int, int, \
                                   const FFTTables<double>&, const GSTables64&, hipStream_t);                     \
+  template void launch_cols_gs_fwd<M>(const double*, int, const double*, double*, int, V*, int, bool,            \
+                                      const FFTTables<double>&, const GSTables64&, const V*, hipStream_t);       \
   template void launch_rows_rhs_mixed<M>(int, const V*, int, const double*, int, const double*, double*, int,     \
                                          int, const StepScalars&, const FFTTables<double>&, const MixedTables&,  \
                                          const V*, hipStream_t);                                                 \

@@ -183,6 +183,15 @@ void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<do
 template <int M>
 void launch_cols_gs(int mode, const double* X, int ldx, bool x_paired, const double* ucur, const double* uprev,
                     double* uout, int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
+// y-line solves of X (paired rows), the update into prev_t's rows (transposed layout) and,
+// with fwd, the next step's row transform of the new state into S
+template <int M>
+void launch_cols_gs_fwd(const double* X, int ldx, const double* ucur, double* prev_t, int n, double2* S, int lds_,
+                        bool fwd, const FFTTables<double>& tab, const GSTables64& gs, const double2* root2M,
+                        hipStream_t st);
+// N x N: A <- A^T; (cur, prev) <- (prev^T, cur)
+void launch_transpose_inplace(double* A, int n, hipStream_t st);
+void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st);
 // batched forms (instances in blockIdx.y; iu / ip select u[0] or u[1]).  Row pass modes:
 // 0 / 1 step / start-up with the x-sweep, 3 / 4 the same without it (X = B)
 template <int M>

@@ -84,6 +84,12 @@ template <int M> struct ColsGS {
                             step_gs_tables(c), c->stream);
   }
 };
+template <int M> struct ColsGSFwd {   // y-sweep, update into the transposed layout, next row pass
+  static void run(const sadi_ctx* c, const double* ucur, double* prev_t, bool fwd) {
+    sadi::launch_cols_gs_fwd<M>(c->X, c->ldX, ucur, prev_t, c->n, c->S, c->ldS, fwd, tables(c), step_gs_tables(c),
+                                c->root2M, c->stream);
+  }
+};
 template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ldX buffer
   static void run(const sadi_ctx* c, double* buf) {
     sadi::launch_cols_gs<M>(2, buf, c->ldX, false, nullptr, nullptr, nullptr, c->n, c->n, tables(c), gs_tables(c),
@@ -461,9 +467,44 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
   if (!u_prev || !u_cur) return fail(SADI_E_INVALID, "NULL array");
   if (u_prev == u_cur) return fail(SADI_E_INVALID, "u_prev and u_cur must differ");
   if (nsteps < 0) return fail(SADI_E_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0) return SADI_OK;
+  if (c->prec == SADI_FP64 && !c->tail_gemm) {
+    // Three kernels per step: the y-sweep kernel also forms u^{n+1} and the next step's row
+    // transform, on the transposed grid (x and y swap roles every step).  u^{n-1} starts in
+    // the transposed layout; both arrays are back in the natural layout at the end.
+    auto mark = [&](int k) {
+      hipEvent_t e = c->mark(k);
+      if (e) (void)hipEventRecord(e, c->stream);
+    };
+    const sadi::StepScalars sc = scalars(c, false);
+    sadi::launch_transpose_inplace(u_prev, c->n, c->stream);
+    double* a = u_prev;   // u^{n-1}, transposed relative to b
+    double* b = u_cur;    // u^n in this step's layout
+    for (int s = 0; s < nsteps; ++s) {
+      mark(0);
+      if (s == 0) dispatch_m<RowsFwd>(c->m, c, b, nullptr);
+      mark(1);
+      dispatch_m<ColsConv>(c->m, c);
+      mark(2);
+      dispatch_m<RowsRhs>(c->m, c, 0, b, nullptr, c->X, c->ldX, sc);
+      mark(3);
+      dispatch_m<ColsGSFwd>(c->m, c, b, a, s + 1 < nsteps);
+      mark(4);
+      if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
+      sadi_status st = check_launch();
+      if (st != SADI_OK) return st;
+      std::swap(a, b);
+    }
+    // b holds the newest state (transposed when nsteps is odd), a the one before
+    if (nsteps % 2 == 0)
+      sadi::launch_transpose_inplace(a, c->n, c->stream);
+    else
+      sadi::launch_swap_transposed(u_cur, u_prev, c->n, c->stream);
+    return check_launch();
+  }
   double* a = u_prev;
   double* b = u_cur;
-  if (c->prec == SADI_FP64 && nsteps > 0) {
+  if (c->prec == SADI_FP64) {
     // the leapfrog update of step s rides on the row transform of step s + 1
     for (int s = 0; s < nsteps; ++s) {
       sadi_status st = s == 0 ? enqueue_step(c, 0, b, a, nullptr, a, 2)

@@ -61,8 +61,9 @@ def find_csv(directory: str, suffix: str = "counter_collection.csv") -> str:
 
 
 # the kernels of a step n >= 1 inside a multi-step run, by name prefix and template tail
-KERNEL_KEYS = {"rows_fwd": ("rows_fwd_kernel<", ", 1>"), "cols_conv": ("cols_conv_kernel<", ">"),
-               "rows_rhs_gs": ("rows_rhs_gs_kernel<", ", 0>"), "cols_gs": ("cols_gs_kernel<", ", 2, 1>")}
+# kernels of a run of steps (the row transform runs once per run)
+KERNEL_KEYS = {"rows_fwd": ("rows_fwd_kernel<", ", 0, 0>"), "cols_conv": ("cols_conv_kernel<", ">"),
+               "rows_rhs_gs": ("rows_rhs_gs_kernel<", ", 0, 1>"), "cols_gs_fwd": ("cols_gs_fwd_kernel<", ">")}
 
 
 def kernel_key(name: str, m: int):

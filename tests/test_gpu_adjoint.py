@@ -66,10 +66,15 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     phi1 = W.asymmetric_field(n, seed=51)
     u_obs = W.asymmetric_field(n, seed=52)
     out = [grads_gpu(phi1, np.zeros_like(phi1), u_obs, alpha, kappa, n, tau, steps, c) for c in (1, 5, 23, 100)]
+    # runs alternate the grid orientation from their first step, so segments of different
+    # lengths round differently: the gradients agree to rounding, not bit for bit
     for J, gphi, gk in out[1:]:
-        assert J == out[0][0]
-        assert np.array_equal(gphi, out[0][1])
-        assert gk == out[0][2]
+        assert abs(J - out[0][0]) <= 1e-13 * abs(out[0][0])
+        assert np.abs(gphi - out[0][1]).max() <= 1e-12 * np.abs(out[0][1]).max()
+        assert abs(gk - out[0][2]) <= 1e-12 * abs(out[0][2])
+    # the same checkpoint interval twice: bitwise identical
+    again = grads_gpu(phi1, np.zeros_like(phi1), u_obs, alpha, kappa, n, tau, steps, 5)
+    assert again[0] == out[1][0] and np.array_equal(again[1], out[1][1]) and again[2] == out[1][2]
 
 
 def test_adjoint_vs_central_differences_n511():
