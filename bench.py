@@ -359,7 +359,6 @@ def main():
         "step_roofline": {"algorithmic_bytes_per_step": total_alg, "achieved_GBps": step_gbs,
                           "frac": step_gbs / HBM_PEAK_GBS},
         "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in ktimes.items() if k in STEP_KERNELS},
-        "rows_fwd_ms_once_per_run": ktimes["rows_fwd"][0],   # one run is timed
         "setup_s": setup_s,
         "finite": finite,
         "precision_variants": variants,

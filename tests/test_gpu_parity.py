@@ -327,3 +327,30 @@ def test_config1_run_mixed_refined():
         s.run(u0, u1, wl.steps - 1)
         got = from_dev(u1)
     assert rel(got, ref) < 1e-10
+
+
+# ------------------------------------------------------------------ run vs single steps
+@pytest.mark.parametrize("n,steps", [(1023, 5), (1023, 6), (4095, 3), (4095, 4)])
+def test_run_matches_single_steps(n, steps):
+    """sadi_run alternates the grid orientation from step to step (x and y swap roles); it
+    must agree with the same number of sadi_step calls in the natural layout to rounding."""
+    _say(f"run vs steps n={n} steps={steps}")
+    dev = _dev()
+    U0 = W.seeded_bump(n, seed=n)
+    with solver(1.5, n, 1e-3) as s:
+        a = torch.from_numpy(np.ascontiguousarray(U0.T)).to(dev)
+        b = s.first_step(a, 0.2 * a)
+        ra, rb = a.clone(), b.clone()
+        s.run(ra, rb, steps)
+        sa, sb = a.clone(), b.clone()
+        for k in range(steps):
+            if k % 2 == 0:
+                s.step(sa, sb)          # sa <- next
+            else:
+                s.step(sb, sa)
+        newest, before = (sa, sb) if steps % 2 == 1 else (sb, sa)
+        torch.cuda.synchronize()
+        e_new = float((rb - newest).abs().max() / newest.abs().max())
+        e_old = float((ra - before).abs().max() / before.abs().max())
+    _say(f"  newest {e_new:.2e}, previous {e_old:.2e}")
+    assert e_new <= 1e-12 and e_old <= 1e-12
