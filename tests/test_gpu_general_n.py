@@ -67,10 +67,11 @@ def test_apply_lh_general_n(n, alpha):
     assert rel(got, P.lh_apply(U)) < 1e-12
 
 
-# N = 19, 39, 99: the rank-(M-N) correction inside the line solves (M - N <= 32); N = 799, 1500,
-# 2100: the solves leave the bordered solutions and one GEMM per sweep corrects all lines
-@pytest.mark.parametrize("n,alpha,g", [(19, 1.5, "neg_sin"), (39, 1.7, "neg_sin"), (99, 1.2, "neg_cube"),
-                                       (799, 1.5, "neg_sin"), (1500, 1.4, "neg_cube"), (2100, 1.6, "neg_sin")])
+# N = 30, 125: the rank-(M-N) correction inside the line solves (M - N <= 3); the others: the
+# solves leave the bordered solutions and one GEMM per sweep corrects all lines
+@pytest.mark.parametrize("n,alpha,g", [(30, 1.5, "neg_sin"), (125, 1.3, "neg_cube"), (19, 1.5, "neg_sin"),
+                                       (39, 1.7, "neg_sin"), (99, 1.2, "neg_cube"), (799, 1.5, "neg_sin"),
+                                       (1500, 1.4, "neg_cube"), (2100, 1.6, "neg_sin")])
 def test_steps_general_n(n, alpha, g):
     _say(f"steps general n={n}")
     tau = 0.02
