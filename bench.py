@@ -79,10 +79,18 @@ def cpu_baseline(wl, sample_steps: int) -> dict:
         dt = time.perf_counter() - t0
         blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     pts = wl.n * wl.n * sample_steps
+    # one thread: two further steps of the same sample
+    with threadpool_limits(limits=1), scipy.fft.set_workers(1):
+        t1 = time.perf_counter()
+        for _ in range(2):
+            prev, cur = cur, P.step_delta(prev, cur, gemm=True)
+        dt1 = time.perf_counter() - t1
     return {"value": pts / dt, "unit": "grid-point-steps/s", "cores": int(max(blas, threads)), "kind": "oracle",
             "sample": f"{sample_steps} steps n>=1 of the same N={wl.n} workload after the start-up step "
                       f"(setup and explicit H^-1 excluded), {dt:.1f} s wall, numpy/scipy FP64 with "
-                      f"{threads} FFT workers and BLAS threads"}
+                      f"{threads} FFT workers and BLAS threads",
+            "single_thread_value": wl.n * wl.n * 2 / dt1,
+            "single_thread_sample": f"2 further steps, 1 FFT worker and 1 BLAS thread, {dt1:.1f} s wall"}
 
 
 def batched_leg(seed: int, count: int, steps: int, unbatched_sample: int) -> dict:
@@ -180,6 +188,39 @@ def adjoint_leg(seed: int) -> dict:
             "grad_phi1_norm": float(x.grad.norm().item())}
 
 
+def config_sweep(seed: int, steps: int) -> list:
+    """The plain FP64 configuration over N in {1023, 2047, 4095} and alpha in {1.2, 1.5, 1.8}
+    (kappa = 1, g = -sin u, seeded Gaussian phi1, phi2 = 0, tau = 1e-3): ms/step of a run
+    after a warm-up run, and the step's algorithmic HBM rate."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2312_06206_amd import Solver
+
+    dev = torch.device("cuda:0")
+    out = []
+    for n in (1023, 2047, 4095):
+        alg = algorithmic_bytes(n)
+        step_bytes = sum(alg[k] for k in STEP_KERNELS)
+        for alpha in (1.2, 1.5, 1.8):
+            wl = W.config2(n, alpha, seed=seed, steps=steps)
+            with Solver(wl.alpha, wl.kappa, wl.n, wl.tau, wl.domain, g=wl.g) as s:
+                u0 = torch.from_numpy(np.ascontiguousarray(wl.phi1().T)).to(dev)
+                u1 = s.first_step(u0, torch.zeros_like(u0))
+                s.run(u0, u1, 10)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.run(u0, u1, steps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                out.append({"N": n, "alpha": alpha, "steps": steps, "ms_per_step": 1e3 * dt / steps,
+                            "value": n * n * steps / dt, "step_alg_GBps": step_bytes * steps / dt / 1e9,
+                            "step_alg_frac": step_bytes * steps / dt / 1e9 / HBM_PEAK_GBS,
+                            "finite": bool(torch.isfinite(u1).all().item())})
+    return out
+
+
 # the paper's own CPU timings (seconds, S-ADI column) and printed errors for two of its
 # workloads: Table 1 (sine-Gordon, h = 1/40, N = 799) and Table 3 (Klein-Gordon, h = 1/50,
 # N = 999), alpha = 1.5, Omega = (-10, 10)^2
@@ -242,11 +283,12 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--no-variants", action="store_true", help="skip the FP32 / FP32+refine runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (uneven N) leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own workloads")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the N x alpha sweep of the FP64 configuration")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -370,6 +412,8 @@ def main():
         out["adjoint"] = adjoint_leg(args.seed)
     if not args.no_paper:
         out["paper_workloads"] = paper_leg()
+    if not args.no_sweep:
+        out["config_sweep"] = config_sweep(args.seed, 300)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
