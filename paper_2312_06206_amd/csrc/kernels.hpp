@@ -73,10 +73,11 @@ __device__ __forceinline__ double g_of(double u, int kind, double p) {
   }
 }
 
-// launch shapes per kernel family
+// launch shapes per kernel family (measured over N = 127..4095 and the uneven batch)
+// row line kernels: one line per workgroup from T = 128 threads per line, else 128 threads
 template <int M> struct RowCfg {
   static constexpr int T = M / Shape<M>::E;
-  static constexpr int LPW = T >= 256 ? 1 : 256 / T;
+  static constexpr int LPW = T >= 128 ? 1 : 128 / T;
   static constexpr bool LINE_FAST = false;
   static constexpr int SPLIT = 2;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
@@ -96,10 +97,11 @@ template <int M> struct RowFwdCfg {
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
 };
 
-// two lines (even / odd frequency halves) per column, 512 threads per workgroup
+// two lines (even / odd frequency halves) per column; 256 threads per workgroup (512 at
+// M = 4096, one column).  Small workgroups spread the few columns of small N over all CUs.
 template <int M> struct ColConvCfg {
   static constexpr int T = M / Shape<M>::E;
-  static constexpr int LPW = (512 / T) < 2 ? 2 : 512 / T;
+  static constexpr int LPW = (256 / T) < 2 ? 2 : 256 / T;
   static constexpr bool LINE_FAST = true;
   static constexpr int SPLIT = 2;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
@@ -107,10 +109,10 @@ template <int M> struct ColConvCfg {
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
 };
 
-// adjacent columns in adjacent lanes, 512 threads per workgroup
+// adjacent columns in adjacent lanes; 256 threads per workgroup (512 at M = 4096)
 template <int M> struct ColGSCfg {
   static constexpr int T = M / Shape<M>::E;
-  static constexpr int LPW = (512 / T) < 2 ? 2 : 512 / T;
+  static constexpr int LPW = (256 / T) < 2 ? 2 : 256 / T;
   static constexpr bool LINE_FAST = true;
   static constexpr int SPLIT = 2;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
