@@ -1157,17 +1157,14 @@ void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg
 // ----------------------------------------------------------------------------------
 // host-side launchers
 template <int M>
-void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, bool x_paired, int ldu, V* S,
-                     int lds_, int n, const FFTTables<double>& tab, const V* root2M, hipStream_t st) {
+void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, V* S, int lds_, int n,
+                     const FFTTables<double>& tab, const V* root2M, hipStream_t st) {
   const int grid = (n + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW;
   const dim3 blk(RowFwdCfg<M>::NT);
   if (hat == nullptr)
     hipLaunchKernelGGL((rows_fwd_kernel<M, 0, 0>), dim3(grid), blk, 0, st, u, uprev, hat, ldx, ldu, S, lds_, n, tab,
                        root2M);
-  else if (x_paired)
-    hipLaunchKernelGGL((rows_fwd_kernel<M, 1, 1>), dim3(grid), blk, 0, st, u, uprev, hat, ldx, ldu, S, lds_, n, tab,
-                       root2M);
-  else
+  else   // the deferred update reads X in plain rows
     hipLaunchKernelGGL((rows_fwd_kernel<M, 1, 0>), dim3(grid), blk, 0, st, u, uprev, hat, ldx, ldu, S, lds_, n, tab,
                        root2M);
 }
@@ -1175,12 +1172,12 @@ void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx,
 // out = 2 ucur - uprev + hat (mode 0, out may alias uprev), out = ucur + hat (mode 1), or
 // (ucur, uprev) <- (2 ucur - uprev + hat, ucur) (mode 2)
 __global__ void __launch_bounds__(256)
-leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict__ hat, int ldx, int xs,
-                double* out, int n) {
+leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict__ hat, int ldx, double* out,
+                int n) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   if (i >= n) return;
   const size_t o = (size_t)j * n + i;
-  const double h = hat[xs ? pair_row(j, ldx) + 2 * i : (size_t)j * ldx + i];   // xs: X in paired rows
+  const double h = hat[(size_t)j * ldx + i];   // X in plain rows
   const double c = ucur[o];
   if (mode == 2) {           // newest into ucur, the current state into uprev
     const double v = 2.0 * c - uprev[o] + h;
@@ -1191,10 +1188,9 @@ leapfrog_kernel(int mode, double* ucur, double* uprev, const double* __restrict_
   }
 }
 
-void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, bool x_paired, double* out,
-                     int n, hipStream_t st) {
-  hipLaunchKernelGGL(leapfrog_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, mode, ucur, uprev, hat, ldx,
-                     x_paired ? 1 : 0, out, n);
+void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, double* out, int n,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(leapfrog_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, mode, ucur, uprev, hat, ldx, out, n);
 }
 
 template <int M>
@@ -1246,20 +1242,18 @@ void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<do
 }
 
 template <int M>
-void launch_cols_gs(int mode, const double* X, int ldx, bool x_paired, const double* ucur, const double* uprev,
-                    double* uout, int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st) {
+void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
+                    int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st) {
   const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
   const int grid = ((ngroups + 7) / 8) * 8;
   double* Xw = const_cast<double*>(X);
-  // modes 0 and 1 read the step's own X (paired rows); mode 2 also serves plain buffers
+  // modes 0 and 1 read a single step's X in paired rows; mode 2 works in place on plain
+  // rows (the four-kernel run of GEMM-corrected contexts, the adjoint's buffers)
   if (mode == 0)
     hipLaunchKernelGGL((cols_gs_kernel<M, 0, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
                        uout, ldu, n, tab, gs, ngroups);
   else if (mode == 1)
     hipLaunchKernelGGL((cols_gs_kernel<M, 1, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
-                       uout, ldu, n, tab, gs, ngroups);
-  else if (x_paired)
-    hipLaunchKernelGGL((cols_gs_kernel<M, 2, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
                        uout, ldu, n, tab, gs, ngroups);
   else
     hipLaunchKernelGGL((cols_gs_kernel<M, 2, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, Xw, ldx, ucur, uprev,
@@ -1367,7 +1361,7 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
 }
 
 #define SADI_INSTANTIATE(M)                                                                                      \
-  template void launch_rows_fwd<M>(const double*, double*, const double*, int, bool, int, V*, int, int,        \
+  template void launch_rows_fwd<M>(const double*, double*, const double*, int, int, V*, int, int,              \
                                    const FFTTables<double>&, const V*, hipStream_t);                             \
   template void launch_cols_conv<M>(V*, int, int, const double*, int, const FFTTables<double>&, const V*,        \
                                     hipStream_t);                                                                \
@@ -1376,7 +1370,7 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
                                       const V*, hipStream_t);                                                    \
   template void launch_rows_gs<M>(double*, int, int, int, const FFTTables<double>&, const GSTables64&,            \
                                   hipStream_t);                                                                  \
-  template void launch_cols_gs<M>(int, const double*, int, bool, const double*, const double*, double*, int, int, \
+  template void launch_cols_gs<M>(int, const double*, int, const double*, const double*, double*, int, int,       \
                                   const FFTTables<double>&, const GSTables64&, hipStream_t);                     \
   template void launch_cols_gs_fwd<M>(const double*, int, const double*, double*, int, V*, int, bool,            \
                                       const FFTTables<double>&, const GSTables64&, const V*, hipStream_t);       \

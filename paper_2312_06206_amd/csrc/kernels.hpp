@@ -165,13 +165,13 @@ struct BatchInst {
   StepScalars sc;           // sigma, gamma carry this instance's kappa, h^-alpha, tau
 };
 
-// hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev);
-// x_paired: hat (pitch ldx) in paired rows, else plain rows
+// hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev),
+// hat in plain rows of pitch ldx
 template <int M>
-void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, bool x_paired, int ldu,
-                     double2* S, int lds_, int n, const FFTTables<double>& tab, const double2* root2M, hipStream_t st);
-void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, bool x_paired, double* out,
-                     int n, hipStream_t st);
+void launch_rows_fwd(const double* u, double* uprev, const double* hat, int ldx, int ldu, double2* S, int lds_,
+                     int n, const FFTTables<double>& tab, const double2* root2M, hipStream_t st);
+void launch_leapfrog(int mode, double* ucur, double* uprev, const double* hat, int ldx, double* out, int n,
+                     hipStream_t st);
 template <int M>
 void launch_cols_conv(double2* S, int lds_, int n, const double* lam, int ldlam, const FFTTables<double>& tab,
                       const double2* root2M, hipStream_t st);
@@ -183,8 +183,8 @@ template <int M>
 void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab, const GSTables64& gs,
                     hipStream_t st);
 template <int M>
-void launch_cols_gs(int mode, const double* X, int ldx, bool x_paired, const double* ucur, const double* uprev,
-                    double* uout, int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
+void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
+                    int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
 // y-line solves of X (paired rows), the update into prev_t's rows (transposed layout) and,
 // with fwd, the next step's row transform of the new state into S
 template <int M>

@@ -62,8 +62,8 @@ namespace {
 
 template <int M> struct RowsFwd {
   static void run(const sadi_ctx* c, const double* u, double* lf_prev) {
-    sadi::launch_rows_fwd<M>(u, lf_prev, lf_prev ? c->X : nullptr, c->ldX, c->x_paired, c->n, c->S, c->ldS, c->n,
-                             tables(c), c->root2M, c->stream);
+    sadi::launch_rows_fwd<M>(u, lf_prev, lf_prev ? c->X : nullptr, c->ldX, c->n, c->S, c->ldS, c->n, tables(c),
+                             c->root2M, c->stream);
   }
 };
 template <int M> struct ColsConv {
@@ -80,8 +80,8 @@ template <int M> struct RowsRhs {
 };
 template <int M> struct ColsGS {
   static void run(const sadi_ctx* c, int mode, const double* ucur, const double* uprev, double* uout) {
-    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, c->x_paired, ucur, uprev, uout, c->n, c->n, tables(c),
-                            step_gs_tables(c), c->stream);
+    sadi::launch_cols_gs<M>(mode, c->X, c->ldX, ucur, uprev, uout, c->n, c->n, tables(c), step_gs_tables(c),
+                            c->stream);
   }
 };
 template <int M> struct ColsGSFwd {   // y-sweep, update into the transposed layout, next row pass
@@ -92,14 +92,13 @@ template <int M> struct ColsGSFwd {   // y-sweep, update into the transposed lay
 };
 template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ldX buffer
   static void run(const sadi_ctx* c, double* buf) {
-    sadi::launch_cols_gs<M>(2, buf, c->ldX, false, nullptr, nullptr, nullptr, c->n, c->n, tables(c), gs_tables(c),
+    sadi::launch_cols_gs<M>(2, buf, c->ldX, nullptr, nullptr, nullptr, c->n, c->n, tables(c), gs_tables(c),
                             c->stream);
   }
 };
 template <int M> struct RowsFwdPitched {  // spectrum of a grid function with row pitch ld
   static void run(const sadi_ctx* c, const double* u, int ld) {
-    sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, false, ld, c->S, c->ldS, c->n, tables(c), c->root2M,
-                             c->stream);
+    sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, ld, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
   }
 };
 template <int M> struct BccbEig {
@@ -203,7 +202,7 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
     if (st != SADI_OK) return st;
     if (cols_mode != 2)
       sadi::launch_leapfrog(cols_mode == 0 ? 0 : 1, const_cast<double*>(ucur), const_cast<double*>(uprev), c->X,
-                            c->ldX, c->x_paired, uout, c->n, c->stream);
+                            c->ldX, uout, c->n, c->stream);
   } else if (c->prec == SADI_FP64) {
     dispatch_m<ColsGS>(c->m, c, cols_mode, ucur, uprev, uout);
   } else
@@ -514,9 +513,9 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
     }
     // the pending update leaves the newest state in u_cur and the one before in u_prev
     if (b == u_cur)
-      sadi::launch_leapfrog(2, b, a, c->X, c->ldX, c->x_paired, nullptr, c->n, c->stream);
+      sadi::launch_leapfrog(2, b, a, c->X, c->ldX, nullptr, c->n, c->stream);
     else
-      sadi::launch_leapfrog(0, b, a, c->X, c->ldX, c->x_paired, a, c->n, c->stream);
+      sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
     return check_launch();
   }
   for (int s = 0; s < nsteps; ++s) {
