@@ -212,8 +212,11 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
   return check_launch();
 }
 
+// a2: the coefficient table a_ij (N x N), or empty with lf: its rank-k factors, multiplied
+// out on the device
 sadi_status build_ctx(double alpha, double kappa, int n, double tau, const double* domain,
-                      const std::vector<double>& a1, const std::vector<double>& a2, sadi_ctx** out) {
+                      const std::vector<double>& a1, const std::vector<double>& a2, const sadi::LapFactors* lf,
+                      sadi_ctx** out) {
   sadi_ctx* c = new (std::nothrow) sadi_ctx();
   if (!c) return fail(SADI_E_NOMEM, "host allocation failed");
   c->n = n;
@@ -343,12 +346,16 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->sig_e, hsig_e.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->sig_o, hsig_o.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
 
-  // ---- eigenvalues of the block-circulant embedding of L_h, on the device with the row
-  // transform: two passes of even-extension DFTs over the uploaded a_ij (temporaries freed)
+  // ---- a_ij on the device (rank-k product on rocBLAS, then the exact corner) unless a table
+  // was given, and the eigenvalues of the block-circulant embedding of L_h with the row
+  // transform: two passes of even-extension DFTs (temporaries freed)
   {
     double* a2d = nullptr;
     double* gt = nullptr;
     double2* spec = nullptr;
+    double* fl = nullptr;
+    double* fr = nullptr;
+    rocblas_handle blas = nullptr;
     auto tmp = [&](void** p, size_t bytes) -> sadi_status {
       hipError_t e = hipMalloc(p, bytes);
       if (e != hipSuccess) {
@@ -358,20 +365,55 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
       return SADI_OK;
     };
     auto drop = [&]() {
-      if (a2d) (void)hipFree(a2d);
-      if (gt) (void)hipFree(gt);
-      if (spec) (void)hipFree(spec);
+      for (void* p : {(void*)a2d, (void*)gt, (void*)spec, (void*)fl, (void*)fr})
+        if (p) (void)hipFree(p);
+      if (blas) (void)rocblas_destroy_handle(blas);
     };
-    if ((st = tmp((void**)&a2d, sizeof(double) * a2.size())) != SADI_OK ||
+    const size_t nn = (size_t)n * n;
+    if ((st = tmp((void**)&a2d, sizeof(double) * nn)) != SADI_OK ||
         (st = tmp((void**)&gt, sizeof(double) * (size_t)(m + 1) * n)) != SADI_OK ||
-        (st = tmp((void**)&spec, sizeof(double2) * (size_t)(m + 2) * c->ldS)) != SADI_OK ||
-        (st = up(a2d, a2.data(), sizeof(double) * a2.size())) != SADI_OK) {
+        (st = tmp((void**)&spec, sizeof(double2) * (size_t)(m + 2) * c->ldS)) != SADI_OK) {
+      drop();
+      return bail(st);
+    }
+    if (lf) {
+      // a2d(i, j) = scale * sum_q L[q][i] R[q][j]: L, R are n x k column-major (rows of n)
+      const size_t fk = (size_t)lf->k * n;
+      if ((st = tmp((void**)&fl, sizeof(double) * fk)) != SADI_OK ||
+          (st = tmp((void**)&fr, sizeof(double) * fk)) != SADI_OK ||
+          (st = up(fl, lf->L.data(), sizeof(double) * fk)) != SADI_OK ||
+          (st = up(fr, lf->R.data(), sizeof(double) * fk)) != SADI_OK) {
+        drop();
+        return bail(st);
+      }
+      const double zero = 0.0;
+      rocblas_status bs = rocblas_create_handle(&blas);
+      if (bs != rocblas_status_success) blas = nullptr;
+      if (bs == rocblas_status_success) bs = rocblas_set_stream(blas, c->stream);
+      if (bs == rocblas_status_success)
+        bs = rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_transpose, n, n, lf->k, &lf->scale, fl, n,
+                           fr, n, &zero, a2d, n);
+      hipError_t e = bs == rocblas_status_success
+                         ? hipMemcpy2DAsync(a2d, sizeof(double) * n, lf->corner.data(), sizeof(double) * lf->nc,
+                                            sizeof(double) * lf->nc, lf->nc, hipMemcpyHostToDevice, c->stream)
+                         : hipSuccess;
+      if (bs != rocblas_status_success || e != hipSuccess) {
+        drop();
+        return bail(fail(SADI_E_DEVICE, std::string("coefficient product: ") +
+                                            (bs != rocblas_status_success ? rocblas_status_to_string(bs)
+                                                                          : hipGetErrorString(e))));
+      }
+    } else if ((st = up(a2d, a2.data(), sizeof(double) * nn)) != SADI_OK) {
       drop();
       return bail(st);
     }
     dispatch_m<BccbEig>(m, c, a2d, gt, spec);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && blas && c->tail_gemm && g_setup_step_gemm) {
+      c->blas = blas;   // kept for the correction GEMMs of the time step
+      blas = nullptr;
+    }
     drop();
     if (e != hipSuccess) return bail(fail(SADI_E_DEVICE, std::string("eigenvalue set-up: ") + hipGetErrorString(e)));
   }
@@ -400,8 +442,8 @@ sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const doub
   if (st != SADI_OK) return st;
   try {
     const std::vector<double> a1 = sadi::riesz_coeffs(alpha, sadi::line_size(n));
-    const std::vector<double> a2 = sadi::laplacian_coeffs(alpha, n, g_setup_threads);
-    return build_ctx(alpha, kappa, n, tau, domain, a1, a2, out);
+    const sadi::LapFactors lf = sadi::laplacian_factors(alpha, n, g_setup_threads);
+    return build_ctx(alpha, kappa, n, tau, domain, a1, {}, &lf, out);
   } catch (const std::bad_alloc&) {
     return fail(SADI_E_NOMEM, "host allocation failed in setup");
   } catch (const std::exception& e) {
@@ -420,7 +462,7 @@ sadi_status sadi_setup_with_coeffs(double alpha, double kappa, int n, double tau
     return fail(SADI_E_UNSUPPORTED, "injected coefficient tables need N + 1 to be a power of two");
   try {
     std::vector<double> v1(a1, a1 + n + 1), v2(a2, a2 + (size_t)n * n);
-    return build_ctx(alpha, kappa, n, tau, domain, v1, v2, out);
+    return build_ctx(alpha, kappa, n, tau, domain, v1, v2, nullptr, out);
   } catch (const std::bad_alloc&) {
     return fail(SADI_E_NOMEM, "host allocation failed in setup");
   } catch (const std::exception& e) {

@@ -182,32 +182,40 @@ std::vector<double> riesz_coeffs(double alpha, int count) {
   return a;
 }
 
-std::vector<double> laplacian_coeffs(double alpha, int n, int nthreads) {
-  if (n <= 0) return {};
+LapFactors laplacian_factors(double alpha, int n, int nthreads) {
+  LapFactors f;
+  if (n <= 0) return f;
   const long double beta = (long double)alpha / 2;
   const long double cb = beta / std::tgamma(1.0L - beta);
   const int nq = (int)std::lround((kSHi - kSLo) / kStep) + 1;
   const int nw = worker_count(nthreads);
+  const int HT = 16;   // Hankel terms of the high tail
+  f.n = n;
+  f.k = nq + HT;
+  f.scale = (double)(-cb);
+  f.L.assign((size_t)f.k * n, 0.0);
+  f.R.assign((size_t)f.k * n, 0.0);
 
-  // node matrix B[q][k] = sqrt(w_q) ive(k, 2 t_q), and the origin integrand
-  std::vector<double> B((size_t)nq * n);
+  // node rows: L[q][k] = R[q][k] = sqrt(w_q) ive(k, 2 t_q), and the origin integrand
   std::vector<long double> orig(nq);
   parallel_for(nq, nw, [&](int q) {
     const double s = kSLo + q * kStep;
     const double t = std::exp(s);
-    double* row = &B[(size_t)q * n];
+    double* row = &f.L[(size_t)q * n];
     ive_all(2.0 * t, n, row);
     const long double w = kStep * std::exp(-beta * s);
     orig[q] = w * one_minus_ive0_sq(t, row[0]);
     const double sw = (double)std::sqrt(w);
     for (int k = 0; k < n; ++k) row[k] *= sw;
+    std::copy(row, row + n, &f.R[(size_t)q * n]);
   });
   long double acc0 = 0.0L;
   for (int q = 0; q < nq; ++q) acc0 += orig[q];
 
-  // Hankel coefficients A_m(k) of ive(k, 2t) = (4 pi t)^-1/2 sum_m A_m(k) t^-m, for the high tail
-  const int HT = 16;
-  std::vector<double> A((size_t)HT * n);
+  // Hankel coefficients A_m(k) of ive(k, 2t) = (4 pi t)^-1/2 sum_m A_m(k) t^-m, for the high
+  // tail: rows nq + p hold L = A_p and R = C_p with C[p][j] = sum_r Wt[p][r] A_r(j), so that
+  // the high tail of (i, j) is sum_p A_p(i) C[p][j] (symmetric: Wt depends on p + r only)
+  double* A = &f.L[(size_t)nq * n];
   for (int k = 0; k < n; ++k) {
     const long double mu = 4.0L * k * k;
     long double term = 1.0L;
@@ -221,9 +229,7 @@ std::vector<double> laplacian_coeffs(double alpha, int n, int nthreads) {
   std::vector<long double> Wt(HT * HT, 0.0L);
   for (int p = 0; p < HT; ++p)
     for (int r = 0; p + r < HT; ++r) Wt[p * HT + r] = geom_tail(-(1.0L + beta + p + r), kSHi, +1) / (4.0L * pi);
-
-  // C[p][j] = sum_r Wt[p][r] A_r(j): the high tail of (i, j) is sum_p A_p(i) C[p][j]
-  std::vector<double> Cht((size_t)HT * n, 0.0);
+  double* Cht = &f.R[(size_t)nq * n];
   for (int p = 0; p < HT; ++p)
     for (int j = 0; j < n; ++j) {
       long double sacc = 0.0L;
@@ -231,49 +237,19 @@ std::vector<double> laplacian_coeffs(double alpha, int n, int nthreads) {
       Cht[(size_t)p * n + j] = (double)sacc;
     }
 
-  std::vector<double> out((size_t)n * n);
-  // sum over nodes (rank-nq symmetric product) + high tail, in blocks of rows; the
-  // upper triangle j >= i is computed and mirrored
-  constexpr int RB = 16;
-  const int nblk = (n + RB - 1) / RB;
-  parallel_for(nblk, nw, [&](int blk) {
-    const int i0 = blk * RB, i1 = std::min(n, i0 + RB);
-    std::vector<double> acc((size_t)RB * n, 0.0);
-    for (int q = 0; q < nq; ++q) {
-      const double* row = &B[(size_t)q * n];
-      for (int i = i0; i < i1; ++i) {
-        const double bi = row[i];
-        if (bi == 0.0) continue;
-        double* a = &acc[(size_t)(i - i0) * n];
-        for (int j = i; j < n; ++j) a[j] += bi * row[j];
-      }
+  // corner i, j < nc: the factor product plus the low tail (small i + j) and the origin,
+  // whose integrand is (1 - ive0^2) t^-beta
+  const int nc = std::min(n, kLowOrders);
+  f.nc = nc;
+  f.corner.assign((size_t)nc * nc, 0.0);
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) {
+      long double acc = 0.0L;
+      for (int q = 0; q < f.k; ++q) acc += (long double)f.L[(size_t)q * n + i] * f.R[(size_t)q * n + j];
+      long double v = -cb * acc;
+      if (i + j > 0 && i + j < kLowOrders) v += -cb * low_tail(series_product(4.0L, std::min(i, j), std::max(i, j)), beta, false);
+      f.corner[(size_t)j * nc + i] = (double)v;
     }
-    for (int p = 0; p < HT; ++p) {
-      const double* cp = &Cht[(size_t)p * n];
-      for (int i = i0; i < i1; ++i) {
-        const double api = A[(size_t)p * n + i];
-        double* a = &acc[(size_t)(i - i0) * n];
-        for (int j = i; j < n; ++j) a[j] += api * cp[j];
-      }
-    }
-    for (int i = i0; i < i1; ++i)
-      for (int j = i; j < n; ++j) {
-        const double v = (double)(-cb * acc[(size_t)(i - i0) * n + j]);
-        out[(size_t)j * n + i] = v;
-        out[(size_t)i * n + j] = v;
-      }
-  });
-  // low tail (small i + j only)
-  for (int i = 0; i < std::min(n, kLowOrders); ++i)
-    for (int j = i; i + j < kLowOrders && j < n; ++j) {
-      if (i + j == 0) continue;
-      const long double lt = low_tail(series_product(4.0L, i, j), beta, false);
-      const double add = (double)(-cb * lt);
-      out[(size_t)j * n + i] += add;
-      if (i != j) out[(size_t)i * n + j] += add;
-    }
-  // origin: (1 - ive0^2) t^-beta; low tail from the series of 1 - e^{-4t} I0^2, high tail
-  // t^-beta minus the Hankel product
   {
     std::vector<long double> c = series_product(4.0L, 0, 0);
     for (auto& v : c) v = -v;
@@ -283,8 +259,42 @@ std::vector<double> laplacian_coeffs(double alpha, int n, int nthreads) {
     for (int p = 0; p < HT; ++p)
       for (int r = 0; p + r < HT; ++r) hi00 += Wt[p * HT + r] * A[(size_t)p * n] * A[(size_t)r * n];
     acc0 += geom_tail(-beta, kSHi, +1) - hi00;
-    out[0] = (double)(cb * acc0);
+    f.corner[0] = (double)(cb * acc0);
   }
+  return f;
+}
+
+std::vector<double> laplacian_coeffs(double alpha, int n, int nthreads) {
+  if (n <= 0) return {};
+  const LapFactors f = laplacian_factors(alpha, n, nthreads);
+  const int nw = worker_count(nthreads);
+  std::vector<double> out((size_t)n * n);
+  // rank-k symmetric product in blocks of rows; the upper triangle j >= i is computed and
+  // mirrored
+  constexpr int RB = 16;
+  const int nblk = (n + RB - 1) / RB;
+  parallel_for(nblk, nw, [&](int blk) {
+    const int i0 = blk * RB, i1 = std::min(n, i0 + RB);
+    std::vector<double> acc((size_t)RB * n, 0.0);
+    for (int q = 0; q < f.k; ++q) {
+      const double* lrow = &f.L[(size_t)q * n];
+      const double* rrow = &f.R[(size_t)q * n];
+      for (int i = i0; i < i1; ++i) {
+        const double li = lrow[i];
+        if (li == 0.0) continue;
+        double* a = &acc[(size_t)(i - i0) * n];
+        for (int j = i; j < n; ++j) a[j] += li * rrow[j];
+      }
+    }
+    for (int i = i0; i < i1; ++i)
+      for (int j = i; j < n; ++j) {
+        const double v = f.scale * acc[(size_t)(i - i0) * n + j];
+        out[(size_t)j * n + i] = v;
+        out[(size_t)i * n + j] = v;
+      }
+  });
+  for (int j = 0; j < f.nc; ++j)
+    for (int i = 0; i < f.nc; ++i) out[(size_t)j * n + i] = f.corner[(size_t)j * f.nc + i];
   return out;
 }
 

@@ -15,6 +15,16 @@ std::vector<double> riesz_coeffs(double alpha, int count);
 // a whole-line trapezoidal rule in s = log t; nthreads workers (0 = hardware).
 std::vector<double> laplacian_coeffs(double alpha, int n, int nthreads = 0);
 
+// The same a_ij as a rank-k product: a_ij = scale * sum_q L[q][i] R[q][j] (rows q of n: the
+// quadrature nodes, then the high-tail Hankel terms), except for the corner i, j < nc,
+// given exactly in corner[j*nc + i] (low-tail series and the origin).
+struct LapFactors {
+  int n = 0, k = 0, nc = 0;
+  double scale = 0.0;
+  std::vector<double> L, R, corner;
+};
+LapFactors laplacian_factors(double alpha, int n, int nthreads = 0);
+
 // First column of T^-1 for the SPD Toeplitz T with first column t[0..m-1]
 // (Levinson-Durbin, extended precision).
 std::vector<long double> toeplitz_first_column_inverse(const std::vector<long double>& t);
