@@ -26,6 +26,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2 (fma) x 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0   # wave64 VALU instructions per second (4 cycles each per SIMD)
 METRIC = "S-ADI grid-point-steps/s at N=4095 (FP64 vs FP32+refine), % HBM roofline"
 
 
@@ -48,6 +50,25 @@ def algorithmic_bytes(n: int) -> dict:
 
 
 STEP_KERNELS = ("cols_conv", "rows_rhs_gs", "cols_gs_fwd")
+
+
+def alu_view(kernel: str, avg_ms: float):
+    """FP64 vector-ALU view of a step kernel from committed rocprofv3 VALU counts (None if
+    they were not taken on the current kernel sources)."""
+    try:
+        from paper_2312_06206_amd import profiling
+        v = profiling.valu_for(kernel)
+    except Exception:
+        v = None
+    if not v:
+        return None
+    t = avg_ms * 1e-3
+    return {"bound": "alu", "kernel": kernel, "fp64_flops_per_launch": v["fp64_flops"],
+            "achieved": v["fp64_flops"] / t / 1e12, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": v["fp64_flops"] / t / 1e12 / FP64_VALU_PEAK_TFLOPS,
+            "valu_insts_per_launch": v["SQ_INSTS_VALU"],
+            "valu_issue_frac": v["SQ_INSTS_VALU"] / t / VALU_ISSUE_PEAK,
+            "source": "profiles/valu_counters_N4095.json (rocprofv3 SQ_INSTS_VALU*)"}
 
 
 def traffic_record(kernel: str):
@@ -404,6 +425,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record(dom)},
         "step_roofline": {"algorithmic_bytes_per_step": total_alg, "achieved_GBps": step_gbs,
                           "frac": step_gbs / HBM_PEAK_GBS},
+        "alu_view": alu_view(dom, avg_ms),
         "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in ktimes.items() if k in STEP_KERNELS},
         "setup_s": setup_s,
         "setup_warm_s": setup_warm_s,

@@ -142,3 +142,39 @@ def write_traffic_summary(fetch_dir: str, write_dir: str, calib_fetch_dir: str, 
     with open(out_json, "w") as f:
         json.dump(rec, f, indent=1)
     return rec
+
+
+VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                 "SQ_INSTS_VALU_FMA_F64")
+
+
+def write_valu_summary(pmc_dir: str, n: int, out_json: str, command: str) -> dict:
+    """Per-dispatch wave-instruction counts of the step kernels from one rocprofv3 --pmc run
+    of SQ_WAVES and the SQ_INSTS_VALU family: all VALU instructions and the FP64 add / mul /
+    fma ones (each a wave64 instruction)."""
+    m = n + 1
+    path = find_csv(pmc_dir)
+    per = {c: _mean_by_kernel(path, c, m) for c in VALU_COUNTERS}
+    rec = {"workload": f"N{n}", "command": command, "source_hash": source_hash(), "kernels": {}}
+    for k in KERNEL_KEYS:
+        if all(k in per[c] for c in VALU_COUNTERS):
+            v = {c: per[c][k] for c in VALU_COUNTERS}
+            # FP64 flops: 64 lanes per wave instruction, an fma counts two
+            v["fp64_flops"] = 64.0 * (v["SQ_INSTS_VALU_ADD_F64"] + v["SQ_INSTS_VALU_MUL_F64"]
+                                      + 2.0 * v["SQ_INSTS_VALU_FMA_F64"])
+            rec["kernels"][k] = v
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+def valu_for(kernel: str, workload: str = "N4095"):
+    """The committed VALU counts of a step kernel, if taken on the current kernel sources."""
+    path = os.path.join(_ROOT, "profiles", f"valu_counters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("kernels", {}).get(kernel)
