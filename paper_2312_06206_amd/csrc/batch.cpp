@@ -92,6 +92,12 @@ template <int M> struct BRowsRhs {
     sadi::launch_batch_rows_rhs<M>(mode, bi, (int)g.members.size(), iu, c->ldS, c->ldX, g.n, tables(c), b->stream);
   }
 };
+template <int M> struct BColsGSFwd {
+  static void run(const sadi_batch* b, const Group& g, const sadi::BatchInst* bi, int ic, int ip) {
+    const sadi_ctx* c = b->ctx[g.members[0]];
+    sadi::launch_batch_cols_gs_fwd<M>(bi, (int)g.members.size(), ic, ip, c->ldX, c->ldS, g.n, tables(c), b->stream);
+  }
+};
 template <int M> struct BColsGS {
   static void run(const sadi_batch* b, const Group& g, const sadi::BatchInst* bi) {
     const sadi_ctx* c = b->ctx[g.members[0]];
@@ -118,12 +124,23 @@ sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
 // one step of every group.  first: start-up step (x0 = u[iu], phi2); otherwise lf selects
 // the deferred update in the row transform (u[ip] <- 2 u[iu] - u[ip] + X, then the step
 // advances u[ip]).  On return X holds each instance's increment.
+// One step for every group.  first: the start-up step (four kernels, the increment left in
+// X).  Otherwise, in a run: dense groups take the four-kernel step whose row pass first
+// applies the previous step's deferred update (lf); FFT groups take three kernels on a
+// grid whose orientation alternates, the state u[su] advanced into u[so] (transposed), and
+// the row transform already in S from the run's start or the step before.
 sadi_status batch_step(sadi_batch* b, bool scratch, bool first, int lf, int iu, int ip) {
   for (Group& g : b->groups) {
     const sadi::BatchInst* bi = scratch ? g.d_scratch_inst : g.d_inst;
+    const int su = lf ? ip : iu;   // the state this step advances
+    if (!first && g.path == SADI_PATH_FFT_GS) {
+      dispatch_m<BColsConv>(g.m, b, g, bi);
+      dispatch_m<BRowsRhs>(g.m, b, g, bi, 0, su);
+      dispatch_m<BColsGSFwd>(g.m, b, g, bi, su, 1 - su);
+      continue;
+    }
     dispatch_m<BRowsFwd>(g.m, b, g, bi, lf, iu, ip);
     dispatch_m<BColsConv>(g.m, b, g, bi);
-    const int su = lf ? ip : iu;   // the state this step advances
     if (g.path == SADI_PATH_FFT_GS) {
       dispatch_m<BRowsRhs>(g.m, b, g, bi, first ? 1 : 0, su);
       dispatch_m<BColsGS>(g.m, b, g, bi);
@@ -136,8 +153,9 @@ sadi_status batch_step(sadi_batch* b, bool scratch, bool first, int lf, int iu, 
   return check_launch();
 }
 
-sadi_status batch_leapfrog(sadi_batch* b, bool scratch, int mode, int ic, int ip) {
+sadi_status batch_leapfrog(sadi_batch* b, bool scratch, int mode, int ic, int ip, bool fft_groups_too = true) {
   for (Group& g : b->groups) {
+    if (!fft_groups_too && g.path == SADI_PATH_FFT_GS) continue;
     const sadi_ctx* c = b->ctx[g.members[0]];
     sadi::launch_batch_leapfrog(mode, scratch ? g.d_scratch_inst : g.d_inst, (int)g.members.size(), ic, ip, c->ldX,
                                 g.n, b->stream);
@@ -148,6 +166,13 @@ sadi_status batch_leapfrog(sadi_batch* b, bool scratch, int mode, int ic, int ip
 // nsteps steps n >= 1 from (u[0], u[1]) = (u^{n-1}, u^n); the result is left the same way
 sadi_status batch_run(sadi_batch* b, bool scratch, int nsteps, bool graph) {
   if (nsteps <= 0) return SADI_OK;
+  // FFT groups: u^{n-1} into the transposed layout, the row transform of u^n into S
+  for (Group& g : b->groups) {
+    if (g.path != SADI_PATH_FFT_GS) continue;
+    const sadi::BatchInst* bi = scratch ? g.d_scratch_inst : g.d_inst;
+    sadi::launch_batch_transpose(bi, (int)g.members.size(), 0, g.n, b->stream);
+    dispatch_m<BRowsFwd>(g.m, b, g, bi, 0, 1, 0);
+  }
   sadi_status st = batch_step(b, scratch, false, 0, 1, 0);
   if (st != SADI_OK) return st;
   int cur = 1, prev = 0;
@@ -179,8 +204,19 @@ sadi_status batch_run(sadi_batch* b, bool scratch, int nsteps, bool graph) {
     if (st != SADI_OK) return st;
     std::swap(cur, prev);
   }
-  // pending: newest = 2 u[cur] - u[prev] + X; leave it in u[1], the step before in u[0]
-  return cur == 1 ? batch_leapfrog(b, scratch, 2, 1, 0) : batch_leapfrog(b, scratch, 0, 0, 1);
+  // FFT groups: the newest state is in u[prev] (transposed when nsteps is odd), the one
+  // before in u[cur]; both go back to the natural layout with the newest in u[1]
+  for (Group& g : b->groups) {
+    if (g.path != SADI_PATH_FFT_GS) continue;
+    const sadi::BatchInst* bi = scratch ? g.d_scratch_inst : g.d_inst;
+    if (prev == 1)
+      sadi::launch_batch_transpose(bi, (int)g.members.size(), 0, g.n, b->stream);
+    else
+      sadi::launch_batch_swap_transposed(bi, (int)g.members.size(), g.n, b->stream);
+  }
+  // dense groups: pending newest = 2 u[cur] - u[prev] + X; leave it in u[1], the step before
+  // in u[0]
+  return cur == 1 ? batch_leapfrog(b, scratch, 2, 1, 0, false) : batch_leapfrog(b, scratch, 0, 0, 1, false);
 }
 
 sadi_status upload_desc(sadi_batch* b, Group& g, bool scratch, const std::vector<double*>& s0,

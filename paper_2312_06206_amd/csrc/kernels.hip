@@ -742,8 +742,9 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
 // u^{n-1} in the transposed layout (its row c is column c here, contiguous).  The new
 // column is stored as row c of prev_t: u^{n+1} in the transposed layout, the layout of the
 // next step.  With `fwd` the same column is then transformed along its length, which is
-// the next step's row transform: its half spectrum goes to row c of S.
-template <int M>
+// the next step's row transform: its half spectrum goes to row c of S.  XS: X in paired
+// rows (single instances) or plain rows (batch members).
+template <int M, int XS>
 __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
                                                  double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_,
                                                  FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M,
@@ -760,7 +761,7 @@ __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, i
   const int cc = live ? col : 0;
   const int t = L.t;
   V d[E];
-  load_column_pair<M, E, T, 1>(L, d, X, cc, ldx, smem, n);
+  load_column_pair<M, E, T, XS>(L, d, X, cc, ldx, smem, n);
   gs_solve(L, d, smem, tab, gs, n);
   // an opaque copy of the lane index: the row indices below are recomputed rather than
   // kept live across the solve from the column load (register pressure)
@@ -802,7 +803,7 @@ __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, i
 // Square N x N transposes in 32 x 32 tiles; block (I, J) with I <= J handles the tile pair
 // {(I, J), (J, I)} (blocks with I > J exit).  transpose_inplace: A <- A^T.  swap_transposed:
 // (cur, prev) <- (prev^T, cur).
-__global__ void __launch_bounds__(256) transpose_inplace_kernel(double* A, int n) {
+__device__ __forceinline__ void transpose_inplace_tiles(double* A, int n) {
   const int I = blockIdx.y, J = blockIdx.x;
   if (I > J) return;
   __shared__ double ta[32][33], tb[32][33];
@@ -826,7 +827,7 @@ __global__ void __launch_bounds__(256) transpose_inplace_kernel(double* A, int n
   }
 }
 
-__global__ void __launch_bounds__(256) swap_transposed_kernel(double* cur, double* prev, int n) {
+__device__ __forceinline__ void swap_transposed_tiles(double* cur, double* prev, int n) {
   const int I = blockIdx.y, J = blockIdx.x;
   if (I > J) return;
   __shared__ double ta[32][33], tb[32][33];
@@ -858,6 +859,18 @@ __global__ void __launch_bounds__(256) swap_transposed_kernel(double* cur, doubl
       prev[(size_t)rb * n + cb] = cb_v[q];
     }
   }
+}
+
+__global__ void __launch_bounds__(256) transpose_inplace_kernel(double* A, int n) { transpose_inplace_tiles(A, n); }
+__global__ void __launch_bounds__(256) swap_transposed_kernel(double* cur, double* prev, int n) {
+  swap_transposed_tiles(cur, prev, n);
+}
+// batched (instance blockIdx.z): u[which] <- u[which]^T; (u[1], u[0]) <- (u[0]^T, u[1])
+__global__ void __launch_bounds__(256) transpose_inplace_batched(const BatchInst* __restrict__ bi, int which, int n) {
+  transpose_inplace_tiles(bi[blockIdx.z].u[which], n);
+}
+__global__ void __launch_bounds__(256) swap_transposed_batched(const BatchInst* __restrict__ bi, int n) {
+  swap_transposed_tiles(bi[blockIdx.z].u[1], bi[blockIdx.z].u[0], n);
 }
 
 // ----------------------------------------------------------------------------------
@@ -976,7 +989,16 @@ __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_fwd_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur, double* __restrict__ prev_t,
                    int n, V* __restrict__ S, int lds_, FFTTables<double> tab, GSTables64 gs,
                    const V* __restrict__ root2M, int ngroups, int fwd) {
-  cols_gs_fwd_body<M>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, ngroups, fwd);
+  cols_gs_fwd_body<M, 1>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, ngroups, fwd);
+}
+// batched: instance blockIdx.y; u[ic] = u^n in this step's layout, u[ip] = u^{n-1} transposed
+template <int M>
+__global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
+cols_gs_fwd_batched(const BatchInst* __restrict__ bi, int ic, int ip, int ldx, int lds_, int n,
+                    FFTTables<double> tab, int ngroups) {
+  const BatchInst& p = bi[blockIdx.y];
+  const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
+  cols_gs_fwd_body<M, 0>(p.X, ldx, p.u[ic], p.u[ip], n, p.S, lds_, tab, gs, tab.root2M, ngroups, 1);
 }
 
 // batched update, instance blockIdx.z, row blockIdx.y:
@@ -1356,6 +1378,25 @@ void launch_batch_cols_gs(const BatchInst* bi, int count, int ldx, int n, const 
   hipLaunchKernelGGL(cols_gs_batched<M>, grid, dim3(ColGSCfg<M>::NT), 0, st, bi, ldx, n, tab, ngroups);
 }
 
+template <int M>
+void launch_batch_cols_gs_fwd(const BatchInst* bi, int count, int ic, int ip, int ldx, int lds_, int n,
+                              const FFTTables<double>& tab, hipStream_t st) {
+  const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
+  const dim3 grid(((ngroups + 7) / 8) * 8, count);
+  hipLaunchKernelGGL(cols_gs_fwd_batched<M>, grid, dim3(ColGSCfg<M>::NT), 0, st, bi, ic, ip, ldx, lds_, n, tab,
+                     ngroups);
+}
+
+void launch_batch_transpose(const BatchInst* bi, int count, int which, int n, hipStream_t st) {
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(transpose_inplace_batched, dim3(nt, nt, count), dim3(256), 0, st, bi, which, n);
+}
+
+void launch_batch_swap_transposed(const BatchInst* bi, int count, int n, hipStream_t st) {
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(swap_transposed_batched, dim3(nt, nt, count), dim3(256), 0, st, bi, n);
+}
+
 void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int ip, int ldx, int n, hipStream_t st) {
   hipLaunchKernelGGL(leapfrog_batched, dim3((n + 255) / 256, n, count), dim3(256), 0, st, bi, mode, ic, ip, ldx, n);
 }
@@ -1388,6 +1429,8 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
   template void launch_batch_rows_rhs<M>(int, const BatchInst*, int, int, int, int, int, const FFTTables<double>&, \
                                          hipStream_t);                                                            \
   template void launch_batch_cols_gs<M>(const BatchInst*, int, int, int, const FFTTables<double>&, hipStream_t); \
+  template void launch_batch_cols_gs_fwd<M>(const BatchInst*, int, int, int, int, int, int,                      \
+                                            const FFTTables<double>&, hipStream_t);                              \
   template void launch_bccb_eigenvalues<M>(const double*, int, double*, int, V*, int, double*, int,              \
                                            const FFTTables<double>&, hipStream_t);
 

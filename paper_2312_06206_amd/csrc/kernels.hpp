@@ -209,6 +209,14 @@ template <int M>
 void launch_batch_cols_gs(const BatchInst* bi, int count, int ldx, int n, const FFTTables<double>& tab,
                           hipStream_t st);
 void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int ip, int ldx, int n, hipStream_t st);
+// y-line solves of X (plain rows), update into u[ip] in the transposed layout and the next
+// step's row transform into S, for every instance
+template <int M>
+void launch_batch_cols_gs_fwd(const BatchInst* bi, int count, int ic, int ip, int ldx, int lds_, int n,
+                              const FFTTables<double>& tab, hipStream_t st);
+// every instance: u[which] <- u[which]^T; (u[1], u[0]) <- (u[0]^T, u[1])
+void launch_batch_transpose(const BatchInst* bi, int count, int which, int n, hipStream_t st);
+void launch_batch_swap_transposed(const BatchInst* bi, int count, int n, hipStream_t st);
 
 // set-up: eigenvalues of the block-circulant embedding of the N x N coefficients a2 (device,
 // row-major, pitch N) into lam ((M+1) rows, pitch ldlam, even ky then odd ky per row kx,
