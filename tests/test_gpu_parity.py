@@ -232,7 +232,7 @@ def test_alpha2_injected_coefficients_dst_closed_form():
 
 
 # ------------------------------------------------------------------ full size
-@pytest.mark.parametrize("alpha", [1.5])
+@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8])
 def test_full_size_step_parity(alpha):
     """N = 4095 (the benchmark's grid): the start-up step and one step n >= 1 against the
     oracle's FFT tier, from identical inputs."""
@@ -255,11 +255,12 @@ def test_full_size_step_parity(alpha):
     assert rel(g2 - 2 * U1 + phi1, U2 - 2 * U1 + phi1) < 1e-10
 
 
-def test_full_size_run_parity():
-    """N = 4095: three steps through sadi_run (the benchmark's launch sequence) against the
-    oracle stepping from the same two states."""
-    wl = W.config2(4095, 1.5, seed=0)
-    _say("full size run parity")
+@pytest.mark.parametrize("n,alpha", [(4095, 1.5), (4095, 1.2), (4095, 1.8), (2047, 1.2), (1023, 1.8)])
+def test_full_size_run_parity(n, alpha):
+    """The FP64 configuration's grids: three steps through sadi_run (the benchmark's launch
+    sequence) against the oracle stepping from the same two states."""
+    wl = W.config2(n, alpha, seed=0)
+    _say(f"full size run parity n={n} alpha={alpha}")
     P = oracle_problem(wl.alpha, wl.n, wl.tau)
     U0 = W.asymmetric_field(wl.n, seed=23) + wl.phi1()
     U1 = U0 + 1e-3 * W.asymmetric_field(wl.n, seed=24)
