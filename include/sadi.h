@@ -221,7 +221,9 @@ sadi_status sadi_batch_first_step(sadi_batch* b);
 
 /* nsteps steps n >= 1 of every instance, in place: on return u_prev, u_cur hold
  * u^{n+nsteps-1}, u^{n+nsteps}.  Asynchronous on the batch stream; no allocation (the
- * first call with graphs enabled captures and instantiates the graph). */
+ * first call with graphs enabled captures and instantiates the graph).  The arrays are
+ * work space while the call runs: groups on the FFT path alternate between the grid and
+ * its transpose from step to step, as sadi_run does. */
 sadi_status sadi_batch_run(sadi_batch* b, int nsteps);
 
 /* enable != 0: sadi_batch_run replays two steps at a time from a captured HIP graph. */
