@@ -1,10 +1,10 @@
 // Device kernels of the S-ADI time step (FP64 path).
 //
 // Grid layout: an N x N grid function u(x_i, y_j) is stored with x fastest,
-// element (i, j) at u[j * ld + i] (row j = the x-line y = y_j).  M = N + 1 is a
-// power of two; P = 2M >= 2N - 1 is the size of the block-circulant embedding of
-// the BTTB operator L_h (section "Fast implementation based on GS formula":
-// L_h u by embedding in a block circulant with circulant blocks and 2D FFT).
+// element (i, j) at u[j * ld + i] (row j = the x-line y = y_j).  M is the smallest power
+// of two >= N + 1; P = 2M >= 2N - 1 is the size of the block-circulant embedding of the
+// BTTB operator L_h (section "Fast implementation based on GS formula": L_h u by
+// embedding in a block circulant with circulant blocks and 2D FFT).
 //
 // Kernels of one step (delta form H Uhat H = B of that section):
 //   rows_fwd   : rFFT_P of every zero-padded x-line          u -> S (N x (M+1) complex)
@@ -14,9 +14,12 @@
 //                (+ tau phi2 in the start-up step); x-line solve H^-1 B -> X
 //   cols_gs    : y-line solve H^-1 on every column of X, then the leapfrog update
 //                u^{n+1} = 2u^n - u^{n-1} + Uhat (start-up: u^1 = u^0 + Uhat)
-// Line solves use the Gohberg-Semencul formula (Proposition 1 / Algorithm 1 of
-// that section) on the bordered system of size M = N + 1, whose first N unknowns
-// follow from a rank-one correction (Schur complement of the bordered matrix).
+// In a run, cols_gs_fwd replaces cols_gs and the next step's rows_fwd: the grid is
+// transposed from one step to the next (x and y swap roles), so the column it solves is
+// a row of the next step's grid.
+// Line solves use the Gohberg-Semencul formula (Proposition 1 / Algorithm 1 of that
+// section) on the bordered system of size M, whose first N unknowns follow from a
+// rank-(M - N) correction (Schur complement of the bordered matrix).
 #include <hip/hip_runtime.h>
 
 #include "fft_core.hpp"

@@ -18,11 +18,20 @@ _ROOT = os.path.dirname(_HERE)
 KERNEL_SOURCES = ("csrc/kernels.hip", "csrc/kernels.hpp", "csrc/fft_core.hpp")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace collapsed: edits to comments or
+    layout do not change the compiled kernels, so they keep committed counters valid."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(_HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(_HERE, rel)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
