@@ -221,32 +221,86 @@ __device__ __forceinline__ void gs_solve(const LineT& L, V2<typename LineT::Real
 }
 
 // y[k] = (beta T(a) x)[k], k = t + T m, for a real line x (FP64): the 2M-point circulant
-// embedding split into its even and odd frequencies,
-//   y = ifft(sig_e o fft(x)) + Q^H ifft(sig_o o fft(Q x)),  Q = diag(e^{-i pi k/M}).
+// embedding of beta T(a), whose eigenvalues s (real, even: s[k + M] = s[M - k]) are stored
+// as even / odd frequencies scaled by 1/(2M).  The real input of length 2M (x, then zeros)
+// is packed as z[j] = x[2j] + i x[2j+1], so one length-M transform each way suffices.
+// With Z = fft(z), E = (Z[k] + conj Z[M-k]) / 2, O = (Z[k] - conj Z[M-k]) / (2i) and
+// W = e^{-i pi/M}: X[k] = E + W^k O and X[k+M] = E - W^k O are the 2M-point spectrum,
+// Y = s X, and Z'[k] = (Y[k] + Y[k+M]) / 2 + i W^-k (Y[k] - Y[k+M]) / 2 gives
+// ifft(Z')[j] = M (y[2j] + i y[2j+1]); the factor 2 sig_(e|o) = s / M absorbs the M.
 template <class LineT>
 __device__ __forceinline__ void toeplitz_apply64(const LineT& L, const float* x, double* y, void* lds,
                                                  const FFTTables<double>& tab, const ToeplitzTables64& toe,
                                                  const double2* __restrict__ q) {
-  constexpr int E = LineT::E, T = LineT::T;
+  constexpr int M = LineT::M, E = LineT::E, T = LineT::T;
   const int t = L.t;
+  double* buf = reinterpret_cast<double*>(lds);
+  V* zb = reinterpret_cast<V*>(lds);
+  // pack: slot c < E/2 holds z[j], j = t + T c; the other slots are the zero half
+#pragma unroll
+  for (int m = 0; m < E; ++m) L.put_real(buf, t + T * m, (double)x[m]);
+  __syncthreads();
   V d[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = V{(double)x[m], 0.0};
-  L.template transform<-1>(d, lds, tab);
-  pointwise_real<E, T>(d, toe.sig_e, t);
-  L.template transform<+1>(d, lds, tab);
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    y[m] = d[m].x;
-    d[m] = V{(double)x[m], 0.0};
+  for (int c = 0; c < E; ++c) {
+    const int j = t + T * c;
+    d[c] = c < E / 2 ? V{L.get_real(buf, 2 * j), L.get_real(buf, 2 * j + 1)} : V{0.0, 0.0};
   }
-  pointwise<E, T, false>(d, q, t);
+  __syncthreads();
   L.template transform<-1>(d, lds, tab);
-  pointwise_real<E, T>(d, toe.sig_o, t);
-  L.template transform<+1>(d, lds, tab);
-  pointwise<E, T, true>(d, q, t);
+  // s[k] / M for 0 <= k <= M
+  auto sig = [&](int k) -> double { return 2.0 * ((k & 1) ? toe.sig_o[k >> 1] : toe.sig_e[k >> 1]); };
+  // Z'[k] from Z[k] and Z[M-k]
+  auto zprime = [&](int k, V zk, V zmk) -> V {
+    const V zm = cconj(zmk);
+    const V e = cscale(cadd(zk, zm), 0.5);
+    const V io = cscale(csub(zk, zm), 0.5);   // i O
+    const V o = V{io.y, -io.x};
+    const V w = k < M ? q[k] : V{-1.0, 0.0};   // W^k
+    const V wo = cmul(w, o);
+    const V ya = cscale(cadd(e, wo), sig(k));       // Y[k]
+    const V yb = cscale(csub(e, wo), sig(M - k));   // Y[k + M]
+    const V ep = cscale(cadd(ya, yb), 0.5);
+    const V op = cmulc(cscale(csub(ya, yb), 0.5), w);
+    return V{ep.x - op.y, ep.y + op.x};
+  };
+  // pairs (k, M - k) through a half-length complex buffer: slots c >= E/2 hold k >= M/2.
+  // The upper half publishes Z; each lower k (0 < k < M/2) forms Z'[k] and Z'[M - k] and
+  // leaves the latter in its partner's place; k = 0 and k = M/2 pair with themselves.
 #pragma unroll
-  for (int m = 0; m < E; ++m) y[m] += d[m].x;
+  for (int c = E / 2; c < E; ++c) zb[L.cidx(t + T * c - M / 2)] = d[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < E / 2; ++c) {
+    const int k = t + T * c;
+    if (k == 0) {
+      d[c] = zprime(0, d[c], d[c]);
+    } else {
+      const int pm = L.cidx(M - k - M / 2);
+      const V zmk = zb[pm];
+      zb[pm] = zprime(M - k, zmk, d[c]);
+      d[c] = zprime(k, d[c], zmk);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = E / 2; c < E; ++c) {
+    const int k = t + T * c;
+    d[c] = k == M / 2 ? zprime(k, d[c], d[c]) : zb[L.cidx(k - M / 2)];
+  }
+  __syncthreads();
+  L.template transform<+1>(d, lds, tab);
+  // unpack: y[2j] = Re, y[2j+1] = Im for j = t + T c < M/2, back to the canonical slots
+#pragma unroll
+  for (int c = 0; c < E / 2; ++c) {
+    const int j = t + T * c;
+    L.put_real(buf, 2 * j, d[c].x);
+    L.put_real(buf, 2 * j + 1, d[c].y);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) y[m] = L.get_real(buf, t + T * m);
+  __syncthreads();
 }
 
 // Mixed-precision line solve.  On entry dv[m] = (v[k], v[M-1-k]) (FP64, v[N] = 0); on exit
