@@ -32,7 +32,7 @@ using V = double2;
 // at least 4 waves per SIMD: <= 128 VGPRs, several workgroups per CU to overlap barriers
 #define SADI_OCC4 __attribute__((amdgpu_waves_per_eu(4, 8)))
 // mixed-precision kernels hold more per-line state: 2 waves per SIMD, <= 256 VGPRs
-#define SADI_OCC2 __attribute__((amdgpu_waves_per_eu(1, 8)))
+#define SADI_OCC2 __attribute__((amdgpu_waves_per_eu(2, 8)))
 
 // ----------------------------------------------------------------------------------
 // Paired row layout: rows y and y + 1 (y even) interleaved, element (y, k) at

@@ -120,7 +120,7 @@ template <int M> struct ColGSCfg {
   static constexpr int LDS_BYTES = Line::LDS_BYTES;
 };
 
-// mixed precision (FP32 solves, optional FP64 residual correction): 1 wave per SIMD,
+// mixed precision (FP32 solves, optional FP64 residual correction): 2 waves per SIMD,
 // 256 threads per workgroup
 template <int M> struct MixRowCfg {
   static constexpr int T = M / Shape<M>::E;
