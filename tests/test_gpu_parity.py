@@ -255,18 +255,32 @@ def test_full_size_step_parity(alpha):
     assert rel(g2 - 2 * U1 + phi1, U2 - 2 * U1 + phi1) < 1e-10
 
 
+_THREE_STEPS = {}
+
+
+def _oracle_three_steps(n, alpha):
+    """Two seeded states on the configuration's grid and the oracle's three steps from
+    them: (u0, u1, u3 prev, u4 cur), cached per (n, alpha)."""
+    key = (n, alpha)
+    if key not in _THREE_STEPS:
+        wl = W.config2(n, alpha, seed=0)
+        P = oracle_problem(wl.alpha, wl.n, wl.tau)
+        U0 = W.asymmetric_field(wl.n, seed=23) + wl.phi1()
+        U1 = U0 + 1e-3 * W.asymmetric_field(wl.n, seed=24)
+        prev, cur = U0, U1
+        for _ in range(3):
+            prev, cur = cur, P.step(prev, cur)
+        _THREE_STEPS.clear()
+        _THREE_STEPS[key] = (wl, U0, U1, prev, cur)
+    return _THREE_STEPS[key]
+
+
 @pytest.mark.parametrize("n,alpha", [(4095, 1.5), (4095, 1.2), (4095, 1.8), (2047, 1.2), (1023, 1.8)])
 def test_full_size_run_parity(n, alpha):
     """The FP64 configuration's grids: three steps through sadi_run (the benchmark's launch
     sequence) against the oracle stepping from the same two states."""
-    wl = W.config2(n, alpha, seed=0)
     _say(f"full size run parity n={n} alpha={alpha}")
-    P = oracle_problem(wl.alpha, wl.n, wl.tau)
-    U0 = W.asymmetric_field(wl.n, seed=23) + wl.phi1()
-    U1 = U0 + 1e-3 * W.asymmetric_field(wl.n, seed=24)
-    prev, cur = U0, U1
-    for _ in range(3):
-        prev, cur = cur, P.step(prev, cur)
+    wl, U0, U1, prev, cur = _oracle_three_steps(n, alpha)
     with solver(wl.alpha, wl.n, wl.tau) as s:
         u0, u1 = to_dev(U0), to_dev(U1)
         s.run(u0, u1, 3)
@@ -274,6 +288,21 @@ def test_full_size_run_parity(n, alpha):
     assert rel(got_cur, cur) < 1e-12
     assert rel(got_prev, prev) < 1e-12
     assert rel(got_cur - 2 * got_prev, cur - 2 * prev) < 1e-11
+
+
+@pytest.mark.parametrize("prec,tol_u", [("fp32_refine", 1e-10), ("fp32", 1e-5)])
+def test_full_size_mixed_run_parity(prec, tol_u):
+    """The mixed-precision configuration (N = 4095, alpha = 1.5): three steps through
+    sadi_run with FP32 line solves, refined or not, against the FP64 oracle."""
+    _say(f"full size mixed run parity {prec}")
+    wl, U0, U1, prev, cur = _oracle_three_steps(4095, 1.5)
+    with solver(wl.alpha, wl.n, wl.tau, precision=prec) as s:
+        u0, u1 = to_dev(U0), to_dev(U1)
+        s.run(u0, u1, 3)
+        got_cur, got_prev = from_dev(u1), from_dev(u0)
+    _say(f"  rel errors {rel(got_cur, cur):.2e} {rel(got_prev, prev):.2e}")
+    assert rel(got_cur, cur) < tol_u
+    assert rel(got_prev, prev) < tol_u
 
 
 # ------------------------------------------------------------------ mixed precision
