@@ -100,9 +100,10 @@ def _mean_by_kernel(path: str, counter: str, m: int) -> dict:
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def write_kernel_stats_summary(stats_csv: str, n: int, out_md: str, command: str) -> dict:
+def write_kernel_stats_summary(stats_csv: str, n: int, out_md: str, command: str,
+                               title: str = "") -> dict:
     """Short markdown table of a `rocprofv3 --kernel-trace --stats` kernel_stats.csv: calls,
-    average and total duration of every kernel, step kernels labelled."""
+    average and total duration of every kernel, FP64 step kernels of length n + 1 labelled."""
     import csv
     m = n + 1
     rows = []
@@ -112,7 +113,7 @@ def write_kernel_stats_summary(stats_csv: str, n: int, out_md: str, command: str
                          float(r.get("Percentage", 0.0))))
     rows.sort(key=lambda r: -r[3])
     steps = {}
-    lines = [f"# Kernel trace, S-ADI FP64, N={n}", "", "Command (from the repository root):", "",
+    lines = [f"# Kernel trace, {title or f'S-ADI FP64, N={n}'}", "", "Command (from the repository root):", "",
              "```", command, "```", "",
              "| kernel | step role | calls | avg us | total ms | % |", "|---|---|---|---|---|---|"]
     for name, calls, avg, tot, pct in rows:
