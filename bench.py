@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own workloads")
     ap.add_argument("--no-sweep", action="store_true", help="skip the N x alpha sweep of the FP64 configuration")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of K steps, reported with their median beside value")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -352,9 +354,9 @@ def main():
     u0 = torch.from_numpy(np.ascontiguousarray(wl.phi1().T)).to(dev)
     phi2 = torch.zeros_like(u0)
     u1 = s.first_step(u0, phi2)
-    steps = args.steps + (args.steps % 2)    # even: the run ends with one in-place transpose
+    steps = args.steps   # exactly K: an odd count ends the run with a swap instead of a transpose
     if args.warmup:
-        s.run(u0, u1, args.warmup + (args.warmup % 2))
+        s.run(u0, u1, args.warmup)
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
@@ -362,6 +364,15 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     finite = bool(torch.isfinite(u1).all().item())
+    # further runs of the same K steps (the state keeps evolving): their median beside the
+    # single timed region above
+    repeat_ms = []
+    for _ in range(args.repeats):
+        t0r = time.perf_counter()
+        s.run(u0, u1, steps)
+        torch.cuda.synchronize()
+        repeat_ms.append(1e3 * (time.perf_counter() - t0r) / steps)
+    finite = finite and bool(torch.isfinite(u1).all().item())
     # per-kernel device times from a separate run bracketed by events (each event costs a
     # few microseconds of device time, so the timed run above records none)
     state = (u0.clone(), u1.clone())
@@ -382,7 +393,7 @@ def main():
             v0 = torch.from_numpy(np.ascontiguousarray(wl.phi1().T)).to(dev)
             v1 = s.first_step(v0, phi2)
             if args.warmup:
-                s.run(v0, v1, args.warmup + (args.warmup % 2))
+                s.run(v0, v1, args.warmup)
             torch.cuda.synchronize()
             t0v = time.perf_counter()
             s.run(v0, v1, steps)
@@ -391,7 +402,7 @@ def main():
             err = float((v1 - ref_final).abs().max() / ref_final.abs().max())
             variants[prec] = {"ms_per_step": 1e3 * dtv / steps, "value": wl.n * wl.n * steps / dtv,
                               "speedup_vs_fp64": dt / dtv, "rel_err_vs_fp64_path": err,
-                              "steps": steps + args.warmup + (args.warmup % 2) + 1}
+                              "steps": steps + args.warmup + 1}
         s.set_options(wl.g, 0.0, "fp64")
 
     n = wl.n
@@ -427,6 +438,8 @@ def main():
                           "frac": step_gbs / HBM_PEAK_GBS},
         "alu_view": alu_view(dom, avg_ms),
         "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in ktimes.items() if k in STEP_KERNELS},
+        "repeats": {"ms_per_step": repeat_ms,
+                    "median_ms_per_step": float(np.median(repeat_ms)) if repeat_ms else None},
         "setup_s": setup_s,
         "setup_warm_s": setup_warm_s,
         "finite": finite,
