@@ -329,8 +329,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the slab decomposition is described in DESIGN.md but not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the slab decomposition across GPUs is designed but not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -51,7 +51,7 @@ typedef enum {
   SADI_E_INVALID = -1,     /* bad argument (range, NULL, size) */
   SADI_E_NOMEM = -2,       /* device or host allocation failed */
   SADI_E_DEVICE = -3,      /* HIP runtime error (launch, copy, earlier async fault) */
-  SADI_E_UNSUPPORTED = -4, /* valid problem this build does not handle (N outside [15, 4095], ...) */
+  SADI_E_UNSUPPORTED = -4, /* valid problem the library does not handle (N outside [15, 4095], ...) */
   SADI_E_STATE = -5        /* NULL or destroyed context */
 } sadi_status;
 
