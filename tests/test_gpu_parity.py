@@ -290,6 +290,26 @@ def test_full_size_run_parity(n, alpha):
     assert rel(got_cur - 2 * got_prev, cur - 2 * prev) < 1e-11
 
 
+def test_full_size_run_parity_cubic():
+    """g = -u^3 (the paper's Klein-Gordon examples) at N = 4095: three steps through
+    sadi_run against the oracle from the same two states."""
+    _say("full size run parity g=neg_cube")
+    wl = W.config2(4095, 1.5, seed=0)
+    P = oracle_problem(wl.alpha, wl.n, wl.tau, g="neg_cube")
+    U0 = W.asymmetric_field(wl.n, seed=25) + wl.phi1()
+    U1 = U0 + 1e-3 * W.asymmetric_field(wl.n, seed=26)
+    prev, cur = U0, U1
+    for _ in range(3):
+        prev, cur = cur, P.step(prev, cur)
+    with solver(wl.alpha, wl.n, wl.tau, g="neg_cube") as s:
+        u0, u1 = to_dev(U0), to_dev(U1)
+        s.run(u0, u1, 3)
+        got_cur, got_prev = from_dev(u1), from_dev(u0)
+    assert rel(got_cur, cur) < 1e-12
+    assert rel(got_prev, prev) < 1e-12
+    assert rel(got_cur - 2 * got_prev, cur - 2 * prev) < 1e-11
+
+
 @pytest.mark.parametrize("prec,tol_u", [("fp32_refine", 1e-10), ("fp32", 1e-5)])
 def test_full_size_mixed_run_parity(prec, tol_u):
     """The mixed-precision configuration (N = 4095, alpha = 1.5): three steps through
