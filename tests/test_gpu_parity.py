@@ -57,7 +57,7 @@ def solver(alpha, n, tau, kappa=1.0, g="neg_sin", domain=(-1.0, 1.0), g_param=0.
 
 # ------------------------------------------------------------------ line solves
 @pytest.mark.parametrize("n,alpha", [(15, 1.5), (31, 1.3), (63, 1.2), (127, 1.6), (255, 1.8), (511, 1.4),
-                                     (1023, 1.5), (2047, 1.5), (4095, 1.5), (4095, 1.8)])
+                                     (1023, 1.5), (2047, 1.5), (4095, 1.2), (4095, 1.5), (4095, 1.8)])
 def test_toeplitz_solve(n, alpha):
     _say(f"toeplitz_solve n={n} alpha={alpha}")
     tau = 1e-3 if n > 63 else 1 / 64
@@ -76,7 +76,8 @@ def test_toeplitz_solve(n, alpha):
 
 
 # ------------------------------------------------------------------ BTTB product
-@pytest.mark.parametrize("n,alpha", [(15, 1.5), (31, 1.1), (63, 1.9), (255, 1.5), (1023, 1.3)])
+@pytest.mark.parametrize("n,alpha", [(15, 1.5), (31, 1.1), (63, 1.9), (255, 1.5), (1023, 1.3),
+                                     (2047, 1.8), (4095, 1.2), (4095, 1.5), (4095, 1.8)])
 def test_apply_lh(n, alpha):
     _say(f"apply_lh n={n} alpha={alpha}")
     P = oracle_problem(alpha, n, 1e-3)
@@ -84,7 +85,12 @@ def test_apply_lh(n, alpha):
     ref = P.lh_apply(U)
     with solver(alpha, n, 1e-3) as s:
         got = from_dev(s.apply_lh(to_dev(U)))
-    assert rel(got, ref) < 1e-13
+    err = rel(got, ref)
+    _say(f"  rel error {err:.2e}")
+    # L_h u is a difference of terms up to h^-alpha sum|a_ij| |u| (about 3e3 |L_h u| at
+    # N = 4095, alpha = 1.2), so two correct FP64 evaluations drift apart with N: the
+    # FP64 bar of one step (1e-12) applies at the benchmark's grid, 1e-13 below it
+    assert err < (1e-12 if n >= 4095 else 1e-13)
 
 
 # ------------------------------------------------------------------ single steps
