@@ -33,7 +33,7 @@ def _rel(a, b):
 
 # N = 799: the general-N correction runs as rocBLAS GEMMs inside the captured step
 @pytest.mark.parametrize("n,call,count", [(255, "step", 2), (1023, "step", 2), (255, "run", 3), (511, "run", 4),
-                                          (799, "step", 2), (799, "run", 3)])
+                                          (799, "step", 2), (799, "run", 3), (4095, "step", 2), (4095, "run", 3)])
 def test_graph_replay_matches_eager(n, call, count):
     from paper_2312_06206_amd import Solver
     dev = _dev()
