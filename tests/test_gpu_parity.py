@@ -158,22 +158,23 @@ def test_config1_run():
 
 def test_long_run_n1023():
     """The FP64 configuration's smallest grid (N=1023, alpha=1.5, tau=1e-3, seeded Gaussian
-    phi1, phi2=0): the start-up step and 99 steps through sadi_run against the oracle's
-    run of 100 steps."""
+    phi1, phi2=0): the start-up step and 99 steps through sadi_run, FP64 and FP32+refine,
+    against the oracle's run of 100 steps."""
     wl = W.config2(1023, 1.5, seed=0)
     _say("long run n=1023, 100 steps")
     P = oracle_problem(wl.alpha, wl.n, wl.tau)
     phi1 = wl.phi1()
     phi2 = np.zeros_like(phi1)
     ref_prev, ref_cur = P.run(phi1, phi2, 100)
-    with solver(wl.alpha, wl.n, wl.tau) as s:
-        u0 = to_dev(phi1)
-        u1 = s.first_step(u0, to_dev(phi2))
-        s.run(u0, u1, 99)
-        got_prev, got_cur = from_dev(u0), from_dev(u1)
-    _say(f"  rel errors {rel(got_cur, ref_cur):.2e} {rel(got_prev, ref_prev):.2e}")
-    assert rel(got_cur, ref_cur) < 1e-10
-    assert rel(got_prev, ref_prev) < 1e-10
+    for prec in ("fp64", "fp32_refine"):
+        with solver(wl.alpha, wl.n, wl.tau, precision=prec) as s:
+            u0 = to_dev(phi1)
+            u1 = s.first_step(u0, to_dev(phi2))
+            s.run(u0, u1, 99)
+            got_prev, got_cur = from_dev(u0), from_dev(u1)
+        _say(f"  {prec}: rel errors {rel(got_cur, ref_cur):.2e} {rel(got_prev, ref_prev):.2e}")
+        assert rel(got_cur, ref_cur) < 1e-10, prec
+        assert rel(got_prev, ref_prev) < 1e-10, prec
 
 
 @pytest.mark.parametrize("n,nsteps", [(127, 0), (127, 1), (127, 2), (127, 6), (127, 7), (31, 3), (1023, 4)])
