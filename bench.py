@@ -414,6 +414,9 @@ def main():
     achieved = alg[dom] / (avg_ms * 1e-3) / 1e9
     total_alg = sum(alg[k] for k in STEP_KERNELS)   # the run's one row transform excluded
     step_gbs = total_alg / (ms_per_step * 1e-3) / 1e9
+    dom_traffic = traffic_record(dom)
+    step_tr = [traffic_record(k) for k in STEP_KERNELS]
+    step_traffic = sum(step_tr) if all(step_tr) else None
 
     out = {
         "metric": METRIC,
@@ -433,9 +436,13 @@ def main():
                                f"tau=1e-3",
                    "N": n, "alpha": wl.alpha, "tau": wl.tau, "precision": "fp64", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record(dom)},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": dom_traffic,
+                     # the measured (counter) bytes over the same launch time
+                     "traffic_GBps": dom_traffic / (avg_ms * 1e-3) / 1e9 if dom_traffic else None},
         "step_roofline": {"algorithmic_bytes_per_step": total_alg, "achieved_GBps": step_gbs,
-                          "frac": step_gbs / HBM_PEAK_GBS},
+                          "frac": step_gbs / HBM_PEAK_GBS,
+                          "counter_bytes_per_step": step_traffic,
+                          "counter_GBps": step_traffic / (ms_per_step * 1e-3) / 1e9 if step_traffic else None},
         "alu_view": alu_view(dom, avg_ms),
         "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in ktimes.items() if k in STEP_KERNELS},
         "repeats": {"ms_per_step": repeat_ms,
