@@ -192,7 +192,7 @@ class Solver:
         return u_prev
 
     def run(self, u_prev, u_cur, nsteps: int):
-        """(u_prev, u_cur) <- (u^{n+k-1}, u^{n+k}) in place."""
+        """From (u_prev, u_cur) = (u^{n-1}, u^n): (u^{n+k-1}, u^{n+k}) in place, k = nsteps."""
         self._bind_stream()
         _check(load_library().sadi_run(self._ctx, ctypes.c_void_p(_grid_ptr(u_prev, self.n)),
                                        ctypes.c_void_p(_grid_ptr(u_cur, self.n)), int(nsteps)))
