@@ -178,6 +178,26 @@ def write_valu_summary(pmc_dir: str, n: int, out_json: str, command: str) -> dic
     return rec
 
 
+def write_pmc_summary(pmc_dirs: list, n: int, out_json: str, commands: list) -> dict:
+    """Mean per-dispatch value of every counter in one or more rocprofv3 --pmc runs, for the
+    step kernels of length n + 1 (one record per kernel, counters merged over the runs)."""
+    import csv
+    m = n + 1
+    rec = {"workload": f"N{n}", "commands": commands, "source_hash": source_hash(), "kernels": {}}
+    for d in pmc_dirs:
+        acc: dict = {}
+        with open(find_csv(d)) as f:
+            for row in csv.DictReader(f):
+                key = kernel_key(row.get("Kernel_Name", ""), m)
+                if key:
+                    acc.setdefault((key, row["Counter_Name"]), []).append(float(row["Counter_Value"]))
+        for (key, c), v in acc.items():
+            rec["kernels"].setdefault(key, {})[c] = sum(v) / len(v)
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 def valu_for(kernel: str, workload: str = "N4095"):
     """The committed VALU counts of a step kernel, if taken on the current kernel sources."""
     path = os.path.join(_ROOT, "profiles", f"valu_counters_{workload}.json")
