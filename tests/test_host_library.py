@@ -33,7 +33,7 @@ def test_host_riesz_coeffs_match_oracle(alpha):
     assert (np.abs(a - r) / np.abs(r)).max() < 1e-15
 
 
-@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8])
+@pytest.mark.parametrize("alpha", [1.01, 1.2, 1.5, 1.8, 1.99])
 def test_host_laplacian_coeffs_match_oracle(alpha):
     n = 700
     a = P.host_laplacian_coeffs(alpha, n)
