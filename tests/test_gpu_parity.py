@@ -57,7 +57,8 @@ def solver(alpha, n, tau, kappa=1.0, g="neg_sin", domain=(-1.0, 1.0), g_param=0.
 
 # ------------------------------------------------------------------ line solves
 @pytest.mark.parametrize("n,alpha", [(15, 1.5), (31, 1.3), (63, 1.2), (127, 1.6), (255, 1.8), (511, 1.4),
-                                     (1023, 1.5), (2047, 1.5), (4095, 1.2), (4095, 1.5), (4095, 1.8)])
+                                     (1023, 1.5), (2047, 1.5), (4095, 1.2), (4095, 1.5), (4095, 1.8),
+                                     (255, 1.01), (255, 1.99)])
 def test_toeplitz_solve(n, alpha):
     _say(f"toeplitz_solve n={n} alpha={alpha}")
     tau = 1e-3 if n > 63 else 1 / 64
@@ -95,7 +96,8 @@ def test_apply_lh(n, alpha):
 
 # ------------------------------------------------------------------ single steps
 @pytest.mark.parametrize("n,alpha,tau,g", [(15, 1.5, 1 / 16, "neg_sin"), (63, 1.5, 1 / 64, "neg_sin"),
-                                          (255, 1.7, 1e-3, "neg_cube"), (1023, 1.2, 1e-3, "neg_sin")])
+                                          (255, 1.7, 1e-3, "neg_cube"), (1023, 1.2, 1e-3, "neg_sin"),
+                                          (127, 1.01, 1e-3, "neg_sin"), (127, 1.99, 1e-3, "neg_sin")])
 def test_first_step_and_step(n, alpha, tau, g):
     _say(f"steps n={n} alpha={alpha} g={g}")
     P = oracle_problem(alpha, n, tau, kappa=1.3, g=g)
