@@ -120,3 +120,28 @@ def test_batch_tune_keeps_state():
         b.run(3)
         for k, m in enumerate(ms):
             assert rel(from_dev(u1[k]), reference(m, 4)[1]) < 1e-11
+
+
+def test_batch_at_the_benchmark_sizes():
+    """Members drawn from the batched workload's sizes (N in {255, 511, 1023}, alpha and
+    kappa from its distributions): the line-sweep path with graph replay, the start-up
+    step and four steps against the oracle's runs."""
+    from paper_2312_06206_amd import Batch
+    _dev()
+    ms = W.batch_members(4, seed=0, n_choices=(255, 511, 1023))   # N = 1023, 511, 1023, 255
+    _say(f"batch at benchmark sizes: {[m.n for m in ms]}")
+    b = Batch([m.n for m in ms], [m.alpha for m in ms], [m.kappa for m in ms], TAU)
+    for n in sorted({m.n for m in ms}):
+        b.set_path(n, "fft_gs")
+    b.set_graph(True)
+    u0 = [to_dev(m.phi1()) for m in ms]
+    u1 = [torch.zeros_like(t) for t in u0]
+    p2 = [to_dev(0.3 * W.asymmetric_field(m.n, seed=m.n)) for m in ms]
+    b.bind(u0, u1, p2)
+    with b:
+        b.first_step()
+        b.run(4)
+        for k, m in enumerate(ms):
+            ref_prev, ref_cur = reference(m, 5)
+            assert rel(from_dev(u1[k]), ref_cur) < 1e-11, (k, m.n)
+            assert rel(from_dev(u0[k]), ref_prev) < 1e-11, (k, m.n)
