@@ -9,8 +9,12 @@ state is resident in HBM before the timed region; setup is timed separately.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Prints one JSON line.  `roofline` covers the kernel with the largest share of the
-step, timed with HIP events on the library's stream inside the timed region;
+Prints one JSON line.  `value` comes from one timed region of exactly K steps; `repeats`
+holds further K-step runs (on a copy of the state) and their median.  `roofline` covers
+the kernel with the largest share of the step: algorithmic bytes per launch over its
+mean launch time, from HIP events on the library's stream in a separate run of the same
+launches (events inside the timed region would cost device time), beside the
+counter-measured bytes when the committed counters match the kernel sources.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
