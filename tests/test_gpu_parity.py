@@ -197,10 +197,10 @@ def test_run_even_and_odd_counts(n, nsteps):
         assert rel(from_dev(u0), ref_prev) < 1e-11
 
 
-def test_energy_conserved_on_gpu():
+@pytest.mark.parametrize("n,alpha,tau,nsteps", [(127, 1.5, 5e-3, 200), (1023, 1.8, 1e-3, 100)])
+def test_energy_conserved_on_gpu(n, alpha, tau, nsteps):
     """g = 0: the discrete energy of the stability proof stays constant along the GPU run."""
-    n, alpha, tau = 127, 1.5, 5e-3
-    _say("energy")
+    _say(f"energy n={n} alpha={alpha}")
     P = oracle_problem(alpha, n, tau, g="zero")
     U0 = W.asymmetric_field(n, seed=9)
     Phi2 = 0.5 * W.asymmetric_field(n, seed=10)
@@ -208,8 +208,9 @@ def test_energy_conserved_on_gpu():
         u0 = to_dev(U0)
         u1 = s.first_step(u0, to_dev(Phi2))
         E0 = P.energy(from_dev(u0), from_dev(u1))
-        s.run(u0, u1, 200)
+        s.run(u0, u1, nsteps)
         E1 = P.energy(from_dev(u0), from_dev(u1))
+    _say(f"  relative drift {abs(E1 - E0) / E0:.2e}")
     assert abs(E1 - E0) <= 1e-12 * E0
 
 
