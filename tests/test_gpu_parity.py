@@ -197,14 +197,15 @@ def test_run_even_and_odd_counts(n, nsteps):
         assert rel(from_dev(u0), ref_prev) < 1e-11
 
 
-@pytest.mark.parametrize("n,alpha,tau,nsteps", [(127, 1.5, 5e-3, 200), (1023, 1.8, 1e-3, 100)])
-def test_energy_conserved_on_gpu(n, alpha, tau, nsteps):
+@pytest.mark.parametrize("n,alpha,tau,nsteps,prec", [(127, 1.5, 5e-3, 200, "fp64"), (1023, 1.8, 1e-3, 100, "fp64"),
+                                                   (127, 1.5, 5e-3, 200, "fp32_refine")])
+def test_energy_conserved_on_gpu(n, alpha, tau, nsteps, prec):
     """g = 0: the discrete energy of the stability proof stays constant along the GPU run."""
-    _say(f"energy n={n} alpha={alpha}")
+    _say(f"energy n={n} alpha={alpha} {prec}")
     P = oracle_problem(alpha, n, tau, g="zero")
     U0 = W.asymmetric_field(n, seed=9)
     Phi2 = 0.5 * W.asymmetric_field(n, seed=10)
-    with solver(alpha, n, tau, g="zero") as s:
+    with solver(alpha, n, tau, g="zero", precision=prec) as s:
         u0 = to_dev(U0)
         u1 = s.first_step(u0, to_dev(Phi2))
         E0 = P.energy(from_dev(u0), from_dev(u1))
