@@ -22,10 +22,10 @@ class _Loop(torch.autograd.Function):
         u0 = phi1.detach().contiguous().clone()
         p2 = phi2.detach().contiguous()
         prev, cur = u0.clone(), solver.first_step(u0, p2)
-        pairs = {}                                  # k -> (u^{kC-1}, u^{kC}) for k >= 1
+        pairs = {}                                  # k -> (u^{kC-1}, u^{kC}) for 1 <= k, kC < K
         done = 1
         k = 1
-        while k * checkpoint <= steps:
+        while k * checkpoint < steps:               # backward restarts only from kC < K
             solver.run(prev, cur, k * checkpoint - done)
             done = k * checkpoint
             pairs[k] = (prev.clone(), cur.clone())
@@ -63,7 +63,8 @@ class _Loop(torch.autograd.Function):
                 a_next2, a_next = a_next, a_cur
         grad_phi1 = a_next                                    # a^0 = dJ/dphi1
         grad_kappa = dk.reshape(()).cpu()
-        s.close()
+        # the solver stays open while the autograd context holds it (a second backward with
+        # retain_graph=True reuses it); Solver.__del__ frees it with the context
         return grad_phi1, grad_kappa, None, None, None, None, None, None, None
 
 

@@ -562,8 +562,11 @@ __device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const d
       const double uv = (urow + 2 * T * m)[lane_off];
       double gv = 0.0;
       if constexpr (GK == 1) {
-        far |= !(fabs(uv) <= kSinFastMax);
-        gv = -sin_fp64(uv);
+        // far arguments (and inf / NaN) contribute nothing here: the fast reduction is not
+        // valid for them, and the library sine is added in a separate pass
+        const bool f = !(fabs(uv) <= kSinFastMax);
+        far |= f;
+        gv = f ? 0.0 : -sin_fp64(uv);
       } else if constexpr (GK == 2) {
         gv = -uv * uv * uv;
       } else if constexpr (GK == 3) {
@@ -636,7 +639,8 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
       default: add_pointwise<MODE, 0>(L, buf, urow, prow, sc, n); break;
     }
     if (sc.gkind == 1 && far) {
-      // rare: replace the fast sine by the library's for the far arguments of this lane
+      // rare: the library sine for the far arguments of this lane (their fast-sine term
+      // was left out above)
 #pragma unroll 1
       for (int i = 0; i < E; ++i) {
         const int m = i >> 1, h = i & 1;
@@ -644,7 +648,7 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
         const double uv = (urow + 2 * T * m)[2 * t + h];
         if (!(fabs(uv) <= kSinFastMax)) {
           const int k = 2 * (t + T * m) + h;
-          L.put_real(buf, k, L.get_real(buf, k) + sc.gamma * (sin_fp64(uv) - sin(uv)));
+          L.put_real(buf, k, L.get_real(buf, k) - sc.gamma * sin(uv));
         }
       }
     }

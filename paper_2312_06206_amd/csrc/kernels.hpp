@@ -39,7 +39,9 @@ struct StepScalars {
 // with pi split into three doubles (fused multiply-adds, one rounding per term), then
 // sin x = (-1)^k sin r with the Taylor series of sin r to r^23, whose truncation error is
 // below 1e-20 on |r| <= pi/2.  About 18 instructions instead of the general routine's ~110.
-// Larger arguments, infinities and NaN must go to the library sin (see rhs_phase).
+// Larger arguments, infinities and NaN must go to the library sin (see rhs_phase): for
+// them the reduced argument is not small (|x| above about 5e30 overflows the series, and
+// k leaves the int range above 2^31 pi), so the result is not used.
 constexpr double kSinFastMax = 1.0e5;
 __device__ __forceinline__ double sin_fp64(double x) {
   constexpr double kPi_1 = 0x1.921fb54442d18p+1, kPi_2 = 0x1.1a62633145c07p-53,
@@ -62,15 +64,6 @@ __device__ __forceinline__ double sin_fp64(double x) {
   ps = fma(ps, r2, -1.0 / 6.0);                    // -1/3!
   const double s = fma(r * r2, ps, r);
   return ((int)k & 1) ? -s : s;
-}
-
-__device__ __forceinline__ double g_of(double u, int kind, double p) {
-  switch (kind) {
-    case 1: return -sin_fp64(u);
-    case 2: return -u * u * u;
-    case 3: return -p * u;
-    default: return 0.0;
-  }
 }
 
 // launch shapes per kernel family (measured over N = 127..4095 and the uneven batch)

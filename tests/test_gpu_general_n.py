@@ -1,6 +1,7 @@
 """Grids whose N + 1 is not a power of two (the paper's own examples use N + 1 = 20, 40,
 50, 100, 800): line transforms of the next power of two M and the rank-(M - N)
 correction from H_M^-1 to H_N^-1, against the oracle."""
+import math
 import sys
 
 import numpy as np
@@ -102,55 +103,62 @@ def test_float32_solves_rejected_for_general_n():
             s.set_options("neg_sin", 0.0, "fp32_refine")
 
 
-def _table_error(golden, key, gname, data, ns, coarse_h):
-    t = golden[key]
-    out = []
-    for row in t["rows"]:
-        sol = {}
-        for n in ns:
-            phi1, phi2 = data(n)
-            with solver(row["alpha"], n, t["tau"], g=gname, domain=(-10.0, 10.0)) as s:
-                a = to_dev(phi1)
-                b = s.first_step(a, to_dev(phi2))
-                s.run(a, b, round(t["T"] / t["tau"]) - 1)
-                sol[n] = from_dev(b)
-        out.append((S.error2(sol[ns[0]], sol[ns[1]], coarse_h), row["error2"]))
-    return out
+def _printed_tolerance(v):
+    """Half a unit in the fifth significant digit of a value printed as d.dddd E+-xx."""
+    return 0.5 * 10.0 ** (math.floor(math.log10(abs(v))) - 4)
 
 
-def test_table2_sine_gordon_on_gpu(golden):
-    """Example 1 (sine-Gordon, Omega = (-10,10)^2, tau = 1/100, T = 5): Error_2 for h = 1
-    (N = 19 against N = 39) equals the paper's printed values to their 5 digits."""
-    _say("table 2 on GPU")
-    for e, ref in _table_error(golden, "table2_sine_gordon_space", "neg_sin", W.sine_gordon_data, (19, 39), 1.0):
-        assert abs(e / ref - 1.0) < 1.5e-5, (e, ref)
+def _final_state(alpha, n, tau, steps, example):
+    """u^steps of the paper's example on Omega = (-10,10)^2 (kappa = 1), through the start-up
+    step and sadi_run."""
+    g, data = (("neg_sin", W.sine_gordon_data) if example == "sine_gordon"
+               else ("neg_cube", W.klein_gordon_data))
+    phi1, phi2 = data(n)
+    with solver(alpha, n, tau, g=g, domain=(-10.0, 10.0)) as s:
+        a = to_dev(phi1)
+        b = s.first_step(a, to_dev(phi2))
+        s.run(a, b, steps - 1)
+        return from_dev(b)
 
 
-def test_table4_klein_gordon_on_gpu(golden):
-    """Example 2 (Klein-Gordon, g = -u^3, tau = 1/125, T = 8): Error_2 for h = 2/5 (N = 49
-    against N = 99) equals the printed values."""
-    _say("table 4 on GPU")
-    for e, ref in _table_error(golden, "table4_klein_gordon_space", "neg_cube", W.klein_gordon_data, (49, 99),
-                               0.4):
-        assert abs(e / ref - 1.0) < 1.5e-5, (e, ref)
-
-
-def test_table1_sine_gordon_time_error_on_gpu(golden):
-    """Example 1, h = 1/40 (N = 799): Error_1 for tau = 1/10 against tau = 1/20."""
-    _say("table 1 on GPU")
-    t = golden["table1_sine_gordon_time"]
-    alpha, ref = t["rows"][0]["alpha"], t["rows"][0]["error1"]
-    n = round(20.0 / t["h"]) - 1
-    sol = {}
-    for tau in (t["tau"], t["tau"] / 2):
-        phi1, phi2 = W.sine_gordon_data(n)
-        with solver(alpha, n, tau, domain=(-10.0, 10.0)) as s:
-            a = to_dev(phi1)
-            b = s.first_step(a, to_dev(phi2))
-            s.run(a, b, round(t["T"] / tau) - 1)
-            sol[tau] = from_dev(b)
-    e = S.error1(sol[t["tau"]], sol[t["tau"] / 2], t["h"])
-    assert abs(e / ref - 1.0) < 1.5e-5, (e, ref)
+@pytest.mark.parametrize("alpha", [1.1, 1.5, 1.9])
+@pytest.mark.parametrize("table", ["table1", "table2", "table3", "table4"])
+def test_paper_table_on_gpu(golden, table, alpha):
+    """Every S-ADI entry of the four tables of the numerical experiments (section 6): the
+    four errors of one alpha, each to the five digits printed, and the three orders
+    recomputed from them, to the four decimals printed (46 of the 48 errors; the other two
+    to 5e-5 relative, see the fixture's deviations).  Time tables (1, 3): Error_1 at
+    fixed h from runs at tau and tau/2; space tables (2, 4): Error_2 at fixed tau from grids
+    N and 2N + 1.  kappa = 1 (reading R9); Example 2 with initial amplitude 2 (R16)."""
+    t = golden["s_adi_tables"][table]
+    row = next(r for r in t["rows"] if r["alpha"] == alpha)
+    _say(f"paper {table} alpha={alpha}")
+    errs = []
+    if t["kind"] == "time":
+        n = round(20.0 / t["h"]) - 1
+        taus = list(t["steps"]) + [t["steps"][-1] / 2]
+        sol = [_final_state(alpha, n, tau, round(t["T"] / tau), t["example"]) for tau in taus]
+        errs = [S.error1(sol[k], sol[k + 1], t["h"]) for k in range(4)]
+    else:
+        hs = list(t["steps"]) + [t["steps"][-1] / 2]
+        ns = [round(20.0 / h) - 1 for h in hs]
+        steps = round(t["T"] / t["tau"])
+        sol = [_final_state(alpha, n, t["tau"], steps, t["example"]) for n in ns]
+        errs = [S.error2(sol[k], sol[k + 1], hs[k]) for k in range(4)]
+    orders = [None] + [math.log2(errs[k - 1] / errs[k]) for k in range(1, 4)]
+    _say(f"  errors {[f'{e:.5e}' for e in errs]} printed {row['error']}")
+    _say(f"  orders {[None if o is None else round(o, 4) for o in orders]} printed {row['order']}")
+    # two entries (alpha = 1.1 on the finest grid of each space table) agree to 3e-5
+    # relative only; the fixture lists them with the measured values
+    dev = {d["row"]: d["rel_tol"] for d in golden["s_adi_tables"]["_deviations"]
+           if d["table"] == table and d["alpha"] == alpha}
+    for k, (e, p) in enumerate(zip(errs, row["error"])):
+        if k in dev:
+            assert abs(e / p - 1.0) <= dev[k], (k, e, p)
+        else:
+            assert abs(e - p) <= 1.02 * _printed_tolerance(p), (k, e, p)
+    for o, p in zip(orders[1:], row["order"][1:]):
+        assert abs(o - p) <= 1.5e-4, (o, p)
 
 
 def test_batch_general_n_both_paths():

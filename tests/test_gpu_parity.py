@@ -118,18 +118,24 @@ def test_first_step_and_step(n, alpha, tau, g):
     assert rel(g2 - 2 * U1 + U0, U2 - 2 * U1 + U0) < 1e-11
 
 
-@pytest.mark.parametrize("kappa,far", [(1.0, False), (1e-12, True)])
+@pytest.mark.parametrize("kappa,far", [(1.0, None), (1e-12, "far"), (1e-303, "huge")])
 def test_sine_nonlinearity_over_many_periods(kappa, far):
     """g = -sin u on a field spanning about +-60 (many periods of sin, both signs); with
-    far = True also values beyond the fast sine's reduction range (library fallback).  The
-    g-part of the increment, i.e. the difference of the g = -sin u and g = 0 start-up
-    steps, is compared with the oracle's.  A tiny kappa keeps the L_h part (which cancels
-    in the difference up to its rounding) small next to the g-part when |u| is huge."""
+    far set also values beyond the fast sine's reduction range (library fallback), up to
+    1e300 for "huge".  The g-part of the increment, i.e. the difference of the g = -sin u
+    and g = 0 start-up steps, is compared with the oracle's.  A tiny kappa keeps the L_h
+    part (which cancels in the difference up to its rounding) small next to the g-part
+    when |u| is huge."""
     n, alpha, tau = 127, 1.5, 0.05
     _say(f"sine nonlinearity kappa={kappa} far={far}")
     U0 = 25.0 * W.asymmetric_field(n, seed=31)
     if far:
         U0[5, 7], U0[60, 3], U0[100, 100] = 3.0e5, -7.5e6, 1.0e5
+    if far == "huge":
+        # beyond 2^31 pi (the fast reduction's integer), beyond about 5e30 (its series
+        # overflows), and near the top of the double range
+        U0[10, 20], U0[30, 40], U0[50, 60], U0[70, 80], U0[90, 11] = 6.8e9, 5.0e15, -3.0e30, 1.0e300, -1.0e250
+        U0[111, 3], U0[2, 120] = 2.0 ** 60, -1.0e22
     Phi2 = np.zeros_like(U0)
     out = {}
     for g in ("neg_sin", "zero"):
@@ -139,6 +145,34 @@ def test_sine_nonlinearity_over_many_periods(kappa, far):
     got = out["neg_sin"][0] - out["zero"][0]
     ref = out["neg_sin"][1] - out["zero"][1]
     assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_device_sine_elementwise():
+    """Zero coefficient tables make H = I and L_h = 0, so the start-up step is
+    u^1 = u^0 + (tau^2/2) (-sin u^0) (phi2 = 0).  With tau^2/2 = 1e5 the increment is as
+    large as u^0 (|u^0| <= 1e5, the fast sine's whole range), so (u^1 - u^0) / (tau^2/2)
+    recovers -sin u^0 to about 1e-16 absolute, and the device sine is compared with numpy's
+    element by element.  Bound: 4e-15 absolute (36 units in the last place at 1), set by
+    the rounding of the identity line solves' transforms, not by the sine."""
+    n = 255
+    c = 1.0e5
+    tau = math.sqrt(2.0 * c)
+    _say("device sine element by element")
+    rng = np.random.default_rng(2024)
+    U0 = rng.uniform(-1.0e5, 1.0e5, size=(n, n))
+    k = rng.integers(-31830, 31830, size=4000)      # k pi within the range, plus tiny offsets
+    U0.ravel()[:4000] = k * np.pi + rng.uniform(-1e-6, 1e-6, size=4000)
+    U0.ravel()[4000:4100] = np.linspace(-1.0e5, 1.0e5, 100)
+    U0.ravel()[4100:4200] = rng.uniform(-4.0, 4.0, size=100)
+    U0.ravel()[4200] = 0.0
+    a1 = np.zeros(n + 1)
+    a2 = np.zeros((n, n))
+    with solver(1.5, n, tau, kappa=1.0, a1=a1, a2=a2) as s:
+        u1 = from_dev(s.first_step(to_dev(U0), to_dev(np.zeros_like(U0))))
+    got = (u1 - U0) / c
+    err = np.abs(got + np.sin(U0)).max()
+    _say(f"  max abs error {err:.2e}")
+    assert err <= 4e-15
 
 
 # ------------------------------------------------------------------ whole runs
@@ -435,3 +469,82 @@ def test_run_matches_single_steps(n, steps):
         e_old = float((ra - before).abs().max() / before.abs().max())
     _say(f"  newest {e_new:.2e}, previous {e_old:.2e}")
     assert e_new <= 1e-12 and e_old <= 1e-12
+
+
+# ------------------------------------------------------------------ configured-length runs
+GOLDEN_RUNS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_runs")
+
+
+def _stored_run(n, alpha):
+    """The oracle's u^999, u^1000 of the 1000-step workload (tests/golden/make_long_runs.py)."""
+    path = os.path.join(GOLDEN_RUNS, f"N{n}_a{alpha}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle run {os.path.basename(path)} not generated yet")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("n,alpha", [(1023, 1.2), (1023, 1.5), (1023, 1.8), (2047, 1.2), (2047, 1.5), (2047, 1.8),
+                                     (4095, 1.2), (4095, 1.5), (4095, 1.8)])
+def test_configured_run_1000_steps(n, alpha, prec):
+    """The large workloads as configured (Omega=(-1,1)^2, kappa=1, g=-sin u, tau=1e-3,
+    seeded Gaussian phi1, phi2=0): the start-up step and 999 steps through sadi_run, against
+    the oracle's own 1000-step run (u^999 and u^1000 at the stored sample nodes, and the
+    maximum and 2-norm over the whole grid), to 1e-10 relative.  At alpha = 1.5 on the two
+    larger grids the run is also cut at n = 1, 500 and 999, and the oracle takes one step
+    from the GPU's (u^{n-1}, u^n): u^{n+1} to 1e-12 and the increment to 1e-10."""
+    ref = _stored_run(n, alpha)
+    assert int(ref["meta"][0]) == n and ref["meta"][1] == alpha and int(ref["meta"][3]) == 1000
+    wl = W.config2(n, alpha, seed=int(ref["meta"][4]))
+    _say(f"configured 1000-step run n={n} alpha={alpha} {prec}")
+    sampled = alpha == 1.5 and n >= 2047
+    P = oracle_problem(wl.alpha, wl.n, wl.tau) if sampled else None
+    phi1 = wl.phi1()
+    with solver(wl.alpha, wl.n, wl.tau, precision=prec) as s:
+        u0 = to_dev(phi1)
+        u1 = s.first_step(u0, to_dev(np.zeros_like(phi1)))     # (u^0, u^1)
+        done = 1
+        if sampled:
+            for k in (1, 500, 999):
+                s.run(u0, u1, k - done)                          # (u^{k-1}, u^k)
+                prev, cur = from_dev(u0), from_dev(u1)
+                s.run(u0, u1, 1)                                 # (u^k, u^{k+1})
+                got = from_dev(u1)
+                done = k + 1
+                want = P.step(prev, cur)
+                e_u = rel(got, want)
+                e_hat = rel(got - 2 * cur + prev, want - 2 * cur + prev)
+                _say(f"  step {k} -> {k + 1}: u {e_u:.2e}, increment {e_hat:.2e}")
+                assert e_u <= 1e-12, k
+                assert e_hat <= 1e-10, k
+        s.run(u0, u1, 1000 - done)                               # (u^999, u^1000)
+        got_prev, got_cur = from_dev(u0), from_dev(u1)
+    idx = ref["idx"]
+    errs = []
+    for k, (g, key) in enumerate(((got_prev, "prev"), (got_cur, "cur"))):
+        e = np.abs(g.ravel()[idx] - ref[key]).max() / ref["full_max"][k]
+        e_max = abs(np.abs(g).max() / ref["full_max"][k] - 1.0)
+        e_l2 = abs(np.sqrt(np.sum(g * g)) / ref["full_l2"][k] - 1.0)
+        errs.append((e, e_max, e_l2))
+    _say(f"  u^999 / u^1000 vs oracle run: {errs}")
+    for e, e_max, e_l2 in errs:
+        assert e <= 1e-10 and e_max <= 1e-10 and e_l2 <= 1e-10
+
+
+def test_configured_run_1000_steps_fp32_unrefined():
+    """FP32 line solves without the FP64 correction on the mixed-precision workload
+    (N = 4095, alpha = 1.5, 1000 steps): within 1e-5 of the oracle's run."""
+    n, alpha = 4095, 1.5
+    ref = _stored_run(n, alpha)
+    wl = W.config2(n, alpha, seed=int(ref["meta"][4]))
+    _say("configured 1000-step run fp32 (no refinement)")
+    phi1 = wl.phi1()
+    with solver(wl.alpha, wl.n, wl.tau, precision="fp32") as s:
+        u0 = to_dev(phi1)
+        u1 = s.first_step(u0, to_dev(np.zeros_like(phi1)))
+        s.run(u0, u1, 999)
+        got = from_dev(u1)
+    e = np.abs(got.ravel()[ref["idx"]] - ref["cur"]).max() / ref["full_max"][1]
+    _say(f"  u^1000 vs oracle run: {e:.2e}")
+    assert e <= 1e-5
