@@ -107,6 +107,21 @@ sadi_status sadi_first_step(sadi_ctx* ctx, const double* phi1, const double* phi
  * on exit u_prev = u^{n+1} (u_cur unchanged). */
 sadi_status sadi_step(sadi_ctx* ctx, double* u_prev, const double* u_cur);
 
+/* Allocation-free form of sadi_step, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, result and stream as sadi_step; allocates nothing (no hipMalloc, no library
+ * call that allocates, no timing events).  The step's work space -- the half spectrum and
+ * the x-sweep result, 16 (N+1)(M+8) + 8 (N+1) M bytes -- lives in a static device array of
+ * 32 MiB instead of the context's buffers.  Each GPU that loads the library holds its own
+ * array until the process ends; its address is looked up at sadi_setup with the context's
+ * device current.  Limits: the work space must fit (N <= 1023) and M - N <= 3
+ * (SADI_E_UNSUPPORTED otherwise, with the sizes in the message); the context's device must
+ * be current (SADI_E_INVALID).  All calls on one GPU share the array and it keeps the last
+ * call's contents (every step writes what it reads, nothing needs clearing): calls that
+ * overlap in time on one GPU -- other streams, contexts or threads -- race and give wrong
+ * results. */
+sadi_status sadi_step_noalloc(sadi_ctx* ctx, double* u_prev, const double* u_cur);
+
 /* nsteps >= 0 steps n >= 1.  On entry (u_prev, u_cur) = (u^{n-1}, u^n); on exit
  * (u_prev, u_cur) = (u^{n+nsteps-1}, u^{n+nsteps}).  Both arrays are work space while
  * the calls run: in float64 the steps alternate between the grid and its transpose (the

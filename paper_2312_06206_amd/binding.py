@@ -49,6 +49,7 @@ def load_library() -> ctypes.CDLL:
         "sadi_set_stream": (I, [VP, VP]),
         "sadi_first_step": (I, [VP, VP, VP, VP]),
         "sadi_step": (I, [VP, VP, VP]),
+        "sadi_step_noalloc": (I, [VP, VP, VP]),
         "sadi_run": (I, [VP, VP, VP, I]),
         "sadi_toeplitz_solve": (I, [VP, VP, I, I]),
         "sadi_apply_lh": (I, [VP, VP, VP]),
@@ -189,6 +190,13 @@ class Solver:
         self._bind_stream()
         _check(load_library().sadi_step(self._ctx, ctypes.c_void_p(_grid_ptr(u_prev, self.n)),
                                         ctypes.c_void_p(_grid_ptr(u_cur, self.n))))
+        return u_prev
+
+    def step_noalloc(self, u_prev, u_cur):
+        """As step(), with the work space in the library's static device array (N <= 1023)."""
+        self._bind_stream()
+        _check(load_library().sadi_step_noalloc(self._ctx, ctypes.c_void_p(_grid_ptr(u_prev, self.n)),
+                                                ctypes.c_void_p(_grid_ptr(u_cur, self.n))))
         return u_prev
 
     def run(self, u_prev, u_cur, nsteps: int):

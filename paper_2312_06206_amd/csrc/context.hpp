@@ -79,6 +79,10 @@ struct sadi_ctx {
   double* sig_e = nullptr;
   double* sig_o = nullptr;
   double* partial = nullptr;   // 4 N partial sums (adjoint inner products)
+  // device the context was set up on, and that device's static work space of
+  // sadi_step_noalloc (null if its address could not be resolved)
+  int device = 0;
+  void* scratch = nullptr;
 
   std::vector<void*> allocs;
 

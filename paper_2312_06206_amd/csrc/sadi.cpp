@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,6 +60,41 @@ sadi_status validate_problem(double alpha, double kappa, int n, double tau, cons
 using namespace sadi_impl;
 
 namespace {
+
+// Work space of sadi_step_noalloc: the half spectrum S and the x-sweep result X of one step,
+// in a static device array instead of the context's buffers.  Every GPU that loads the
+// library holds its own copy until the process ends.  In host code `scratch` only names the
+// symbol; its device address is looked up once per device (resolve_scratch, called by
+// set-up with the context's device current) and only that address is used.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (nullptr if it cannot be resolved)
+void* resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();   // leave no error behind for the next call
+      return nullptr;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
+}
+
+// bytes of the step's work space in the static array: S (rows in pairs), 256-byte aligned,
+// then X
+size_t noalloc_s_bytes(const sadi_ctx* c) {
+  return (sizeof(double2) * (size_t)(c->n + 1) * c->ldS + 255) & ~size_t(255);
+}
+size_t noalloc_bytes(const sadi_ctx* c) { return noalloc_s_bytes(c) + sizeof(double) * (size_t)(c->n + 1) * c->ldX; }
 
 template <int M> struct RowsFwd {
   static void run(const sadi_ctx* c, const double* u, double* lf_prev) {
@@ -425,6 +461,9 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     if ((st = tail_correct(c, false)) != SADI_OK || (st = tail_correct(c, true)) != SADI_OK) return bail(st);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(SADI_E_DEVICE, "correction set-up"));
   }
+  // the static work space of sadi_step_noalloc on this device
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SADI_E_DEVICE, "hipGetDevice"));
+  c->scratch = resolve_scratch(c->device);
   *out = c;
   return SADI_OK;
 }
@@ -501,6 +540,36 @@ sadi_status sadi_step(sadi_ctx* c, double* u_prev, const double* u_cur) {
   if (!u_prev || !u_cur) return fail(SADI_E_INVALID, "NULL array");
   if (u_prev == u_cur) return fail(SADI_E_INVALID, "u_prev and u_cur must differ");
   return enqueue_step(c, 0, u_cur, u_prev, nullptr, u_prev);
+}
+
+sadi_status sadi_step_noalloc(sadi_ctx* c, double* u_prev, const double* u_cur) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  if (!u_prev || !u_cur) return fail(SADI_E_INVALID, "NULL array");
+  if (u_prev == u_cur) return fail(SADI_E_INVALID, "u_prev and u_cur must differ");
+  if (c->tail_gemm)
+    return fail(SADI_E_UNSUPPORTED, "sadi_step_noalloc: M - N = " + std::to_string(c->r) +
+                                        " > 3 (that correction runs as a library GEMM)");
+  if (noalloc_bytes(c) > kScratchBytes)
+    return fail(SADI_E_UNSUPPORTED, "sadi_step_noalloc: N = " + std::to_string(c->n) + " needs " +
+                                        std::to_string(noalloc_bytes(c)) + " bytes of work space, more than the " +
+                                        std::to_string(kScratchBytes) + " of the static array (N <= 1023)");
+  int dev = -1;
+  SADI_HIP(hipGetDevice(&dev));
+  if (dev != c->device) return fail(SADI_E_INVALID, "sadi_step_noalloc: the context's device must be current");
+  if (!c->scratch) return fail(SADI_E_DEVICE, "sadi_step_noalloc: the static work space has no device address");
+  // the step's kernels take S and X from the context: point them at the static array for
+  // this call (arguments are captured at launch) and restore the context's own buffers
+  double2* own_s = c->S;
+  double* own_x = c->X;
+  const bool timing = c->timing;
+  c->S = static_cast<double2*>(c->scratch);
+  c->X = reinterpret_cast<double*>(static_cast<unsigned char*>(c->scratch) + noalloc_s_bytes(c));
+  c->timing = false;   // no timing events: they are created on demand
+  const sadi_status st = enqueue_step(c, 0, u_cur, u_prev, nullptr, u_prev);
+  c->S = own_s;
+  c->X = own_x;
+  c->timing = timing;
+  return st;
 }
 
 sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
