@@ -34,8 +34,8 @@
  * H_N^-1 through the Schur complement, H_N^-1 v = w[0:N] - F w[N:M] with w = H_M^-1 [v; 0]
  * and F = -H_N^-1 H_M[0:N, N:M]: a rank-one correction when N + 1 = M (the fast case),
  * rank M - N otherwise.  In the time step a correction of rank above 3 is applied to all
- * lines at once by a rocBLAS GEMM per sweep (each call then also uses rocBLAS on the context
- * stream).  The float32 line solves need N + 1 = M.
+ * lines at once by one matrix-core product per sweep (the library's own kernel, on the
+ * context stream).  The float32 line solves need N + 1 = M.
  */
 #ifndef SADI_H
 #define SADI_H

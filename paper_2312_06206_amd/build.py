@@ -28,6 +28,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 SOURCES = [
     ("kernels.hip", "hip"),
+    ("gemm.hip", "hip"),
     ("sadi.cpp", "hip"),
     ("batch.cpp", "hip"),
     ("setup_math.cpp", "c++"),
@@ -56,7 +57,7 @@ def build(verbose: bool = True) -> str:
         _run(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lrocblas", "-lpthread"])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

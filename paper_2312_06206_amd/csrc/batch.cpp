@@ -2,10 +2,9 @@
 // Instances are grouped by N; each group runs every phase of a step as one launch over all
 // of its instances (blockIdx.y), and a run of steps can be replayed from a captured HIP
 // graph.  Per group, the two line sweeps take either the Gohberg-Semencul FFT kernels or
-// two dense products with the explicit H^-1 (rocBLAS batched DGEMM); a timing pass picks
-// the faster one.
+// two dense products with the explicit H^-1 (batched matrix-core products); a timing pass
+// picks the faster one.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <map>
@@ -27,13 +26,11 @@ struct Group {
   sadi::BatchInst* d_scratch_inst = nullptr;  // same, state in scratch buffers (timing)
   int path = SADI_PATH_FFT_GS;
   double ms[2] = {-1.0, -1.0};                // timed ms per step for each path
-  // dense path: H^-1 per member and rocBLAS pointer arrays (A = H^-1, B = X, T = S as real)
+  // dense path: H^-1 per member (rows H^-1 e_k) and the pointer triples of the two
+  // products per member: T = X H^-1 into the spectrum buffer S (as real), then X = H^-1 T
   std::vector<double*> hinv;
-  const double** d_hinv = nullptr;
-  const double** d_x_in = nullptr;
-  double** d_x_out = nullptr;
-  const double** d_t_in = nullptr;
-  double** d_t_out = nullptr;
+  sadi::GemmPtrs* d_prod1 = nullptr;
+  sadi::GemmPtrs* d_prod2 = nullptr;
 };
 
 }  // namespace
@@ -48,7 +45,6 @@ struct sadi_batch {
   std::vector<const double*> phi2;
   bool bound = false;
   std::vector<Group> groups;
-  rocblas_handle blas = nullptr;
   std::vector<void*> allocs;
   bool use_graph = false;
   hipGraphExec_t pair_exec = nullptr;         // two steps n >= 1 of a run (both buffer parities)
@@ -105,20 +101,16 @@ template <int M> struct BColsGS {
   }
 };
 
-// the two sweeps X <- H^-1 B H^-1 by dense products: in column-major terms the row-major
-// N x N array B (pitch ldX) is B^T, and the x- then y-sweep give T = H^-1 B^T, U^T = T H^-1
+// the two sweeps X <- H^-1 B H^-1 by dense products on the matrix cores.  Row k of the
+// stored inverse is H^-1 e_k, so Hinv[k][j] = (H^-1)[j][k]: the x-sweep of every row of B is
+// T = B Hinv, the y-sweep of every column of T is X[i][c] = sum_k (H^-1)[i][k] T[k][c], i.e.
+// A(i, k) = Hinv[k][i] (column-contiguous A)
 sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
   const sadi_ctx* c = b->ctx[g.members[0]];
-  const double one = 1.0, zero = 0.0;
   const int n = g.n, cnt = (int)g.members.size();
-  rocblas_status st = rocblas_dgemm_batched(b->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
-                                            g.d_hinv, n, g.d_x_in, c->ldX, &zero, g.d_t_out, c->ldX, cnt);
-  if (st == rocblas_status_success)
-    st = rocblas_dgemm_batched(b->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, g.d_t_in,
-                               c->ldX, g.d_hinv, n, &zero, g.d_x_out, c->ldX, cnt);
-  if (st != rocblas_status_success)
-    return fail(SADI_E_DEVICE, std::string("rocblas_dgemm_batched: ") + rocblas_status_to_string(st));
-  return SADI_OK;
+  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod1, cnt, true, c->ldX, n, c->ldX, 1.0, 0.0, b->stream);
+  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod2, cnt, false, n, c->ldX, c->ldX, 1.0, 0.0, b->stream);
+  return check_launch();
 }
 
 // one step of every group.  first: start-up step (x0 = u[iu], phi2); otherwise lf selects
@@ -254,7 +246,6 @@ sadi_status set_scalars(sadi_batch* b, Group& g, bool first) {
 
 void destroy_batch(sadi_batch* b) {
   b->drop_graph();
-  if (b->blas) (void)rocblas_destroy_handle(b->blas);
   for (void* p : b->allocs) (void)hipFree(p);
   for (sadi_ctx* c : b->ctx)
     if (c) (void)sadi_destroy(c);
@@ -300,7 +291,6 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
       pool.emplace_back([&, w] {
         (void)hipSetDevice(device);   // the caller's device, as for sadi_setup
         g_setup_threads = inner;
-        g_setup_step_gemm = false;   // members step through the batched kernels only
         for (int i = w; i < count; i += workers) {
           status[i] = sadi_setup(alpha[i], kappa[i], n[i], tau, domain, &b->ctx[i]);
           if (status[i] != SADI_OK) errors[i] = sadi_last_error();
@@ -320,12 +310,6 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
   }
   b->stream = b->own_stream;
   for (sadi_ctx* c : b->ctx) c->stream = b->stream;
-  if (rocblas_create_handle(&b->blas) != rocblas_status_success) {
-    b->blas = nullptr;
-    return bail(fail(SADI_E_DEVICE, "rocblas_create_handle"));
-  }
-  (void)rocblas_set_stream(b->blas, b->stream);
-  (void)rocblas_set_pointer_mode(b->blas, rocblas_pointer_mode_host);
 
   std::map<int, int> by_n;
   for (int i = 0; i < count; ++i) {
@@ -352,27 +336,22 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
     std::vector<double> eye(nn, 0.0);
     for (int j = 0; j < g.n; ++j) eye[(size_t)j * g.n + j] = 1.0;
     g.hinv.resize(cnt);
-    std::vector<const double*> ha(cnt), hx(cnt), ht(cnt);
+    std::vector<sadi::GemmPtrs> p1(cnt), p2(cnt);
     for (size_t k = 0; k < cnt; ++k) {
       sadi_ctx* c = b->ctx[g.members[k]];
       if ((st = b->alloc((void**)&g.hinv[k], sizeof(double) * nn)) != SADI_OK) return bail(st);
       if (hipMemcpy(g.hinv[k], eye.data(), sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(SADI_E_DEVICE, "hipMemcpy"));
       if ((st = sadi_toeplitz_solve(c, g.hinv[k], g.n, g.n)) != SADI_OK) return bail(st);
-      ha[k] = g.hinv[k];
-      hx[k] = c->X;
-      ht[k] = reinterpret_cast<const double*>(c->S);   // N x ldX doubles fit in the spectrum buffer
+      double* t = reinterpret_cast<double*>(c->S);   // N x ldX doubles fit in the spectrum buffer
+      p1[k] = sadi::GemmPtrs{c->X, g.hinv[k], t};
+      p2[k] = sadi::GemmPtrs{g.hinv[k], t, c->X};
     }
-    const size_t pb = sizeof(double*) * cnt;
-    if ((st = b->alloc((void**)&g.d_hinv, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_x_in, pb)) != SADI_OK ||
-        (st = b->alloc((void**)&g.d_x_out, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_t_in, pb)) != SADI_OK ||
-        (st = b->alloc((void**)&g.d_t_out, pb)) != SADI_OK)
+    const size_t pb = sizeof(sadi::GemmPtrs) * cnt;
+    if ((st = b->alloc((void**)&g.d_prod1, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_prod2, pb)) != SADI_OK)
       return bail(st);
-    if (hipMemcpy(g.d_hinv, ha.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g.d_x_in, hx.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g.d_x_out, hx.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g.d_t_in, ht.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g.d_t_out, ht.data(), pb, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(g.d_prod1, p1.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_prod2, p2.data(), pb, hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(SADI_E_DEVICE, "hipMemcpy"));
   }
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(SADI_E_DEVICE, "setup synchronisation"));

@@ -2,7 +2,6 @@
 // batched entry points.  Not part of the C ABI.
 #pragma once
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <cmath>
 #include <initializer_list>
@@ -21,9 +20,6 @@ bool finite_all(std::initializer_list<double> v);
 bool supported_n(int n);
 // host threads for the set-up maths of the calling thread (0: all hardware threads)
 extern thread_local int g_setup_threads;
-// whether set-up prepares the GEMM of large corrections (rocBLAS handle and a first call)
-// for the single-instance time step; batch members never take that path
-extern thread_local bool g_setup_step_gemm;
 // argument checks of sadi_setup (allow2: alpha = 2 accepted, for injected tables)
 sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2);
 }  // namespace sadi_impl
@@ -60,14 +56,13 @@ struct sadi_ctx {
   double* X = nullptr;         // N rows x ldX (M rows when the correction is a GEMM)
   int ldX = 0;
   // Corrections of rank r > kTailGemmMinRank: the line solves leave the bordered solution of
-  // size M and one GEMM per sweep applies the rank-r correction to all lines.  X then keeps
-  // plain rows (the GEMM addresses it as a matrix); otherwise rows are paired.  Measured:
-  // the per-line correction costs 0.03 ms/step at r = 2 (N = 4094) but 0.2 ms at r = 8 and
-  // 1.0 ms at r = 32, where the GEMM path costs 0.12-0.14 ms.
+  // size M and one matrix-core product per sweep applies the rank-r correction to all lines.
+  // X then keeps plain rows (the product addresses it as a matrix); otherwise rows are
+  // paired.  Measured: the per-line correction costs 0.03 ms/step at r = 2 (N = 4094) but
+  // 0.2 ms at r = 8 and 1.0 ms at r = 32, where the product path costs 0.12-0.14 ms.
   static constexpr int kTailGemmMinRank = 3;
   bool tail_gemm = false;
   bool x_paired = true;
-  rocblas_handle blas = nullptr;   // created at set-up (single instances)
   // mixed precision: FP32 copies of the FFT and Gohberg-Semencul tables, FP64 eigenvalues
   // of the 2M-circulant embedding of beta T(a) (even / odd frequencies, scaled by 1/(2M))
   float2* rootM32 = nullptr;
@@ -103,8 +98,6 @@ struct sadi_ctx {
     return SADI_OK;
   }
   void release() {
-    if (blas) (void)rocblas_destroy_handle(blas);
-    blas = nullptr;
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);

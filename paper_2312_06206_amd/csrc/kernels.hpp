@@ -158,6 +158,18 @@ struct BatchInst {
   StepScalars sc;           // sigma, gamma carry this instance's kappa, h^-alpha, tau
 };
 
+// Dense FP64 products on the matrix cores: C = alpha A B + beta C (k may be 0: C = beta C).
+// C(i, j) at C[i ldc + j]; B(k, j) at B[k ldb + j]; A(i, k) at A[i lda + k] (a_rows) or at
+// A[k lda + i].  batch: device array of count pointer triples (blockIdx.z), or null to use
+// `single`.  No element of C may also be an element of A or B (they may share a buffer).
+struct GemmPtrs {
+  const double* A;
+  const double* B;
+  double* C;
+};
+void launch_dgemm(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* batch, int count, bool a_rows,
+                  long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st);
+
 // hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev),
 // hat in plain rows of pitch ldx
 template <int M>

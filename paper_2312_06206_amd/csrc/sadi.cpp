@@ -20,7 +20,6 @@ namespace sadi_impl {
 
 thread_local std::string g_last_error;
 thread_local int g_setup_threads = 0;
-thread_local bool g_setup_step_gemm = true;
 
 sadi_status fail(sadi_status st, const std::string& msg) {
   g_last_error = msg;
@@ -178,28 +177,18 @@ template <int M> struct RowsGSMixed {
 // Rank-r correction of every line of X from its bordered solution w (size M, the step's
 // sweeps ran with r = 0): x = w[0:N] - F w[N:M] with F stored as r rows of N (section
 // "Fast implementation based on GS formula" solves at size M; the Schur complement of the
-// bordered matrix gives H_N^-1).  rows: X[y][k] -= sum_j X[y][N+j] F[j][k]; columns:
-// X[k][c] -= sum_j F[j][k] X[N+j][c].  In column-major terms X^T is M x N (pitch ldX) and
-// G = F^T is N x r (pitch N).
+// bordered matrix gives H_N^-1).  One matrix-core product per sweep:
+//   rows:    X[y][k] -= sum_j X[y][N + j] F[j][k]   (C = X[:, 0:N], A = X[:, N:M], B = F)
+//   columns: X[k][c] -= sum_j F[j][k] X[N + j][c]   (C = X[0:N, :], A = F^T, B = X[N:M, :])
 sadi_status tail_correct(sadi_ctx* c, bool columns) {
-  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
-    c->blas = nullptr;
-    return fail(SADI_E_DEVICE, "rocblas_create_handle");
-  }
-  rocblas_status st = rocblas_set_stream(c->blas, c->stream);
-  const double minus_one = -1.0, one = 1.0;
   const int n = c->n, r = c->r, ld = c->ldX;
-  if (st == rocblas_status_success) {
-    if (!columns)   // (X^T)[0:N, :] -= G (X^T)[N:M, :]
-      st = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, n, r, &minus_one, c->f, n,
-                         c->X + n, ld, &one, c->X, ld);
-    else            // (X^T)[:, 0:N] -= (X^T)[:, N:M] G^T
-      st = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, n, n, r, &minus_one,
-                         c->X + (size_t)n * ld, ld, c->f, n, &one, c->X, ld);
-  }
-  if (st != rocblas_status_success)
-    return fail(SADI_E_DEVICE, std::string("rocblas_dgemm: ") + rocblas_status_to_string(st));
-  return SADI_OK;
+  if (!columns)
+    sadi::launch_dgemm(n, n, r, sadi::GemmPtrs{c->X + n, c->f, c->X}, nullptr, 1, true, ld, n, ld, -1.0, 1.0,
+                       c->stream);
+  else
+    sadi::launch_dgemm(n, n, r, sadi::GemmPtrs{c->f, c->X + (size_t)n * ld, c->X}, nullptr, 1, false, n, ld, ld,
+                       -1.0, 1.0, c->stream);
+  return check_launch();
 }
 
 // one step of the delta form on the device; mode 0: uout = 2 ucur - uprev + Uhat,
@@ -382,7 +371,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->sig_e, hsig_e.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->sig_o, hsig_o.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
 
-  // ---- a_ij on the device (rank-k product on rocBLAS, then the exact corner) unless a table
+  // ---- a_ij on the device (rank-k product on the matrix cores, then the exact corner) unless a table
   // was given, and the eigenvalues of the block-circulant embedding of L_h with the row
   // transform: two passes of even-extension DFTs (temporaries freed)
   {
@@ -391,7 +380,6 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     double2* spec = nullptr;
     double* fl = nullptr;
     double* fr = nullptr;
-    rocblas_handle blas = nullptr;
     auto tmp = [&](void** p, size_t bytes) -> sadi_status {
       hipError_t e = hipMalloc(p, bytes);
       if (e != hipSuccess) {
@@ -403,7 +391,6 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     auto drop = [&]() {
       for (void* p : {(void*)a2d, (void*)gt, (void*)spec, (void*)fl, (void*)fr})
         if (p) (void)hipFree(p);
-      if (blas) (void)rocblas_destroy_handle(blas);
     };
     const size_t nn = (size_t)n * n;
     if ((st = tmp((void**)&a2d, sizeof(double) * nn)) != SADI_OK ||
@@ -422,22 +409,16 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
         drop();
         return bail(st);
       }
-      const double zero = 0.0;
-      rocblas_status bs = rocblas_create_handle(&blas);
-      if (bs != rocblas_status_success) blas = nullptr;
-      if (bs == rocblas_status_success) bs = rocblas_set_stream(blas, c->stream);
-      if (bs == rocblas_status_success)
-        bs = rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_transpose, n, n, lf->k, &lf->scale, fl, n,
-                           fr, n, &zero, a2d, n);
-      hipError_t e = bs == rocblas_status_success
-                         ? hipMemcpy2DAsync(a2d, sizeof(double) * n, lf->corner.data(), sizeof(double) * lf->nc,
-                                            sizeof(double) * lf->nc, lf->nc, hipMemcpyHostToDevice, c->stream)
-                         : hipSuccess;
-      if (bs != rocblas_status_success || e != hipSuccess) {
+      // a2d[j n + i] = scale sum_q L[q][i] R[q][j]: row j of the product R^T L (matrix cores)
+      sadi::launch_dgemm(n, n, lf->k, sadi::GemmPtrs{fr, fl, a2d}, nullptr, 1, false, n, n, n, lf->scale, 0.0,
+                         c->stream);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(a2d, sizeof(double) * n, lf->corner.data(), sizeof(double) * lf->nc,
+                             sizeof(double) * lf->nc, lf->nc, hipMemcpyHostToDevice, c->stream);
+      if (e != hipSuccess) {
         drop();
-        return bail(fail(SADI_E_DEVICE, std::string("coefficient product: ") +
-                                            (bs != rocblas_status_success ? rocblas_status_to_string(bs)
-                                                                          : hipGetErrorString(e))));
+        return bail(fail(SADI_E_DEVICE, std::string("coefficient product: ") + hipGetErrorString(e)));
       }
     } else if ((st = up(a2d, a2.data(), sizeof(double) * nn)) != SADI_OK) {
       drop();
@@ -446,20 +427,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     dispatch_m<BccbEig>(m, c, a2d, gt, spec);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess && blas && c->tail_gemm && g_setup_step_gemm) {
-      c->blas = blas;   // kept for the correction GEMMs of the time step
-      blas = nullptr;
-    }
     drop();
     if (e != hipSuccess) return bail(fail(SADI_E_DEVICE, std::string("eigenvalue set-up: ") + hipGetErrorString(e)));
-  }
-  // ---- large corrections: the rocBLAS handle and one call of each GEMM now, so that the
-  // time step itself allocates nothing
-  if (c->tail_gemm && g_setup_step_gemm) {
-    if (hipMemsetAsync(c->X, 0, sizeof(double) * (size_t)m * c->ldX, c->stream) != hipSuccess)
-      return bail(fail(SADI_E_DEVICE, "hipMemsetAsync"));
-    if ((st = tail_correct(c, false)) != SADI_OK || (st = tail_correct(c, true)) != SADI_OK) return bail(st);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(SADI_E_DEVICE, "correction set-up"));
   }
   // the static work space of sadi_step_noalloc on this device
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SADI_E_DEVICE, "hipGetDevice"));

@@ -31,7 +31,7 @@ def _rel(a, b):
     return float((a - b).abs().max() / b.abs().max())
 
 
-# N = 799: the general-N correction runs as rocBLAS GEMMs inside the captured step
+# N = 799: the general-N correction runs as matrix-core products inside the captured step
 @pytest.mark.parametrize("n,call,count", [(255, "step", 2), (1023, "step", 2), (255, "run", 3), (511, "run", 4),
                                           (799, "step", 2), (799, "run", 3), (4095, "step", 2), (4095, "run", 3)])
 def test_graph_replay_matches_eager(n, call, count):
