@@ -142,6 +142,7 @@ def batched_leg(seed: int, count: int, steps: int, unbatched_sample: int) -> dic
     t0 = time.perf_counter()
     groups = b.tune(steps=5)
     tune_s = time.perf_counter() - t0
+    schedule, ms_groups, ms_lists = b.schedule()
     b.set_graph(True)
     b.first_step()
     b.run(4)                                   # warm-up (captures the graph)
@@ -168,11 +169,19 @@ def batched_leg(seed: int, count: int, steps: int, unbatched_sample: int) -> dic
         one_ms += 1e3 * (time.perf_counter() - t1) / unbatched_sample
         s.close()
     batch_ms = 1e3 * dt / steps
+    # compulsory bytes of a step of every instance on the Gohberg-Semencul path (the three
+    # kernels of a run step); dense-path groups move more (two N^3 products re-read H^-1)
+    alg = sum(sum(algorithmic_bytes(m.n)[k] for k in STEP_KERNELS) for m in ms)
+    alg_gbs = alg / (batch_ms * 1e-3) / 1e9
     return {"workload": f"{count} instances, N uniform over {{127,255,511,1023}}, alpha~U(1.1,1.9), "
                         f"kappa~U(0.5,2), seeded Gaussian phi1, phi2=0, tau=1e-3, seed {seed}",
             "steps": steps, "ms_per_step": batch_ms, "value": pts * steps / dt, "unit": "grid-point-steps/s",
             "one_by_one_ms_per_step": one_ms, "speedup_vs_one_by_one": one_ms / batch_ms,
-            "groups": groups, "setup_s": setup_s, "tune_s": tune_s, "graph": True, "finite": finite,
+            "groups": groups, "schedule": schedule,
+            "tuned_ms_per_step": {"groups": ms_groups, "work_lists": ms_lists},
+            "roofline": {"bound": "hbm", "algorithmic_bytes_per_step": alg, "achieved": alg_gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg_gbs / HBM_PEAK_GBS},
+            "setup_s": setup_s, "tune_s": tune_s, "graph": True, "finite": finite,
             "one_by_one_sample_steps": unbatched_sample}
 
 

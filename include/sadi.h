@@ -201,8 +201,9 @@ sadi_status sadi_adjoint_step(sadi_ctx* c, int mode, const double* u_prev, const
 /* ---------------------------------------------------------------------------------
  * Batches: many independent problems of the same scheme (same tau, domain and g = -sin u,
  * FP64), each with its own N, alpha and kappa, advanced together.  Instances with equal N
- * form a group; every phase of a step (the four passes of the delta form above) is one
- * launch over all instances of a group.  The two line sweeps of a group take one of two
+ * form a group; every phase of a step (the passes of the delta form above) is one launch
+ * over all instances of a group, or one launch over several groups (see
+ * sadi_batch_set_schedule).  The two line sweeps of a group take one of two
  * paths:
  *   SADI_PATH_FFT_GS  the Gohberg-Semencul line solves (Proposition 1, Algorithm 1);
  *   SADI_PATH_DENSE   X = H^-1 B H^-1 as two batched FP64 matrix products with the explicit
@@ -248,8 +249,20 @@ sadi_status sadi_batch_set_graph(sadi_batch* b, int enable);
  * SADI_PATH_DENSE above dense_max_n). */
 sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path);
 
+/* Schedule of the step's launches: 1 (default) -- the groups on SADI_PATH_FFT_GS with
+ * M <= 2048 share one launch per phase (column convolution, row pass with the x-sweep,
+ * y-sweep with the next row transform), each workgroup taking its instance and block from a
+ * device work list ordered so that an instance stays on one XCD and the XCDs get equal work;
+ * other groups (SADI_PATH_DENSE, M = 4096) are launched on their own; 0 -- every group is
+ * launched on its own. */
+sadi_status sadi_batch_set_schedule(sadi_batch* b, int schedule);
+/* The current schedule and the tuned milliseconds per step of schedules 0 and 1 (-1: not
+ * timed).  Any pointer may be NULL. */
+sadi_status sadi_batch_get_schedule(const sadi_batch* b, int* schedule, double* ms_groups, double* ms_lists);
+
 /* Autotuner: for every group, time `steps` steps of each available path on zero scratch
- * state (the bound state is not touched) and keep the faster path.  Host-synchronous. */
+ * state (the bound state is not touched) and keep the faster path; then time the whole step
+ * under both schedules with those paths and keep the faster schedule.  Host-synchronous. */
 sadi_status sadi_batch_tune(sadi_batch* b, int steps);
 
 /* Group `index` (0 <= index < groups): its N, member count, current path and the tuned

@@ -69,6 +69,8 @@ def load_library() -> ctypes.CDLL:
         "sadi_batch_set_graph": (I, [VP, I]),
         "sadi_batch_set_path": (I, [VP, I, I]),
         "sadi_batch_tune": (I, [VP, I]),
+        "sadi_batch_set_schedule": (I, [VP, I]),
+        "sadi_batch_get_schedule": (I, [VP, P(I), DP, DP]),
         "sadi_batch_get_group": (I, [VP, I, P(I), P(I), P(I), DP, DP]),
         "sadi_batch_get_info": (I, [VP, P(I), P(I), P(ctypes.c_longlong)]),
         "sadi_batch_synchronize": (I, [VP]),
@@ -263,6 +265,7 @@ class Solver:
 
 # ---- batches ---------------------------------------------------------------------
 PATHS = {"fft_gs": 0, "dense": 1}
+SCHEDULES = {"groups": 0, "work_lists": 1}
 
 
 class Batch:
@@ -326,6 +329,18 @@ class Batch:
 
     def set_path(self, n: int, path: str):
         _check(load_library().sadi_batch_set_path(self._h, int(n), PATHS[path]))
+
+    def set_schedule(self, schedule: str):
+        """"work_lists": FFT groups up to M = 2048 share one launch per phase; "groups":
+        every group launched on its own."""
+        _check(load_library().sadi_batch_set_schedule(self._h, SCHEDULES[schedule]))
+
+    def schedule(self):
+        """(current schedule, tuned ms per step of "groups", of "work_lists"; -1 if not timed)."""
+        sc, m0, m1 = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(load_library().sadi_batch_get_schedule(self._h, ctypes.byref(sc), ctypes.byref(m0), ctypes.byref(m1)))
+        names = {v: k for k, v in SCHEDULES.items()}
+        return names[sc.value], m0.value, m1.value
 
     def tune(self, steps: int = 5):
         _check(load_library().sadi_batch_tune(self._h, int(steps)))

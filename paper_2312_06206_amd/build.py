@@ -46,16 +46,21 @@ def _run(cmd):
 
 
 def build(verbose: bool = True) -> str:
+    """Compile every source (concurrently, one compiler process each) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src, lang in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, "-c", "-x", lang, os.path.join(CSRC, src), "-o", obj] + COMMON
         if lang == "hip":
             cmd += DEVICE
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as pool:
+        for f in [pool.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)

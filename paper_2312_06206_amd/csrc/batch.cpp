@@ -45,6 +45,20 @@ struct sadi_batch {
   std::vector<const double*> phi2;
   bool bound = false;
   std::vector<Group> groups;
+  // descriptors of all instances (indexed like the creation arrays), bound state and the
+  // tuner's scratch state, and the host copies they are uploaded from
+  sadi::BatchInst* d_all = nullptr;
+  sadi::BatchInst* d_all_scratch = nullptr;
+  std::vector<sadi::BatchInst> h_all, h_all_scratch;
+  // Work lists: every FFT-path group with M <= kWorkListMaxM takes each phase of the step in
+  // one launch shared with the other such groups (schedule 1); schedule 0 launches every
+  // group separately.  The tuner picks the schedule.
+  int schedule = 1;
+  sadi::WorkItem* d_items[3] = {nullptr, nullptr, nullptr};
+  int n_items[3] = {0, 0, 0};
+  size_t items_cap = 0;
+  std::vector<char> in_list;                  // per group: covered by the work lists
+  double ms_schedule[2] = {-1.0, -1.0};       // tuned ms per step of each schedule
   std::vector<void*> allocs;
   bool use_graph = false;
   hipGraphExec_t pair_exec = nullptr;         // two steps n >= 1 of a run (both buffer parities)
@@ -113,6 +127,69 @@ sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
   return check_launch();
 }
 
+bool wl_eligible(const Group& g) { return g.path == SADI_PATH_FFT_GS && g.m <= sadi::kWorkListMaxM; }
+
+// The three work lists of the current paths.  Whole instances are spread over the 8 XCDs by
+// cost (largest first to the least loaded), so that the column groups of one instance share
+// that XCD's L2; dispatch sends slot 8 q + x to XCD x, so slot 8 q + x holds the q-th item of
+// XCD x's list (empty items pad the shorter lists).
+sadi_status build_worklists(sadi_batch* b) {
+  b->in_list.assign(b->groups.size(), 0);
+  for (int ph = 0; ph < 3; ++ph) b->n_items[ph] = 0;
+  if (b->schedule == 0) return SADI_OK;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) b->in_list[gi] = wl_eligible(b->groups[gi]) ? 1 : 0;
+  for (int ph = 0; ph < 3; ++ph) {
+    struct Inst {
+      int idx, blocks;
+      double cost;
+    };
+    std::vector<Inst> insts;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      if (!b->in_list[gi]) continue;
+      const Group& g = b->groups[gi];
+      int blocks[3];
+      double cost[3];
+      sadi::worklist_shape(g.m, g.n, blocks, cost);
+      for (int i : g.members) insts.push_back(Inst{i, blocks[ph], blocks[ph] * cost[ph]});
+    }
+    if (insts.empty()) continue;
+    std::stable_sort(insts.begin(), insts.end(), [](const Inst& a, const Inst& c) { return a.cost > c.cost; });
+    std::vector<std::vector<sadi::WorkItem>> xcd(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const Inst& in : insts) {
+      const int x = (int)(std::min_element(load, load + 8) - load);
+      load[x] += in.cost;
+      for (int blk = 0; blk < in.blocks; ++blk) xcd[x].push_back(sadi::WorkItem{in.idx, blk});
+    }
+    size_t len = 0;
+    for (auto& v : xcd) len = std::max(len, v.size());
+    std::vector<sadi::WorkItem> items(8 * len, sadi::WorkItem{-1, 0});
+    for (size_t q = 0; q < len; ++q)
+      for (int x = 0; x < 8; ++x)
+        if (q < xcd[x].size()) items[8 * q + x] = xcd[x][q];
+    if (items.size() > b->items_cap) {
+      for (int p = 0; p < 3; ++p) {
+        if (b->d_items[p]) (void)hipFree(b->d_items[p]);
+        b->d_items[p] = nullptr;
+      }
+      b->items_cap = 0;
+      for (int p = 0; p < 3; ++p) {
+        void* q = nullptr;
+        if (hipMalloc(&q, sizeof(sadi::WorkItem) * items.size()) != hipSuccess)
+          return fail(SADI_E_NOMEM, "work list allocation");
+        b->d_items[p] = (sadi::WorkItem*)q;
+      }
+      b->items_cap = items.size();
+      // the lists of the other phases are rebuilt below
+      for (int p = 0; p < ph; ++p) b->n_items[p] = 0;
+      return build_worklists(b);
+    }
+    SADI_HIP(hipMemcpy(b->d_items[ph], items.data(), sizeof(sadi::WorkItem) * items.size(), hipMemcpyHostToDevice));
+    b->n_items[ph] = (int)items.size();
+  }
+  return SADI_OK;
+}
+
 // one step of every group.  first: start-up step (x0 = u[iu], phi2); otherwise lf selects
 // the deferred update in the row transform (u[ip] <- 2 u[iu] - u[ip] + X, then the step
 // advances u[ip]).  On return X holds each instance's increment.
@@ -122,9 +199,17 @@ sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
 // grid whose orientation alternates, the state u[su] advanced into u[so] (transposed), and
 // the row transform already in S from the run's start or the step before.
 sadi_status batch_step(sadi_batch* b, bool scratch, bool first, int lf, int iu, int ip) {
-  for (Group& g : b->groups) {
+  const int su = lf ? ip : iu;   // the state this step advances
+  const bool lists = !first && b->in_list.size() == b->groups.size();
+  if (lists && (b->n_items[0] > 0 || b->n_items[1] > 0 || b->n_items[2] > 0)) {
+    const sadi::BatchInst* all = scratch ? b->d_all_scratch : b->d_all;
+    for (int ph = 0; ph < 3; ++ph)
+      sadi::launch_worklist(ph, all, b->d_items[ph], b->n_items[ph], su, 1 - su, b->stream);
+  }
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    Group& g = b->groups[gi];
+    if (lists && b->in_list[gi]) continue;   // done by the work lists
     const sadi::BatchInst* bi = scratch ? g.d_scratch_inst : g.d_inst;
-    const int su = lf ? ip : iu;   // the state this step advances
     if (!first && g.path == SADI_PATH_FFT_GS) {
       dispatch_m<BColsConv>(g.m, b, g, bi);
       dispatch_m<BRowsRhs>(g.m, b, g, bi, 0, su);
@@ -229,9 +314,24 @@ sadi_status upload_desc(sadi_batch* b, Group& g, bool scratch, const std::vector
     d.f = c->f;
     d.r = c->r;
     d.sc = scalars(c, false);
+    d.n = c->n;
+    d.m = c->m;
+    d.lds = c->ldS;
+    d.ldx = c->ldX;
+    d.ldlam = c->ldlam;
+    d.tab = tables(c);
+    (scratch ? b->h_all_scratch : b->h_all)[i] = d;
   }
   sadi::BatchInst* dst = scratch ? g.d_scratch_inst : g.d_inst;
   SADI_HIP(hipMemcpy(dst, h.data(), sizeof(sadi::BatchInst) * h.size(), hipMemcpyHostToDevice));
+  return SADI_OK;
+}
+
+// the descriptor array of all instances (after upload_desc of every group)
+sadi_status upload_all(sadi_batch* b, bool scratch) {
+  const std::vector<sadi::BatchInst>& h = scratch ? b->h_all_scratch : b->h_all;
+  SADI_HIP(hipMemcpy(scratch ? b->d_all_scratch : b->d_all, h.data(), sizeof(sadi::BatchInst) * h.size(),
+                     hipMemcpyHostToDevice));
   return SADI_OK;
 }
 
@@ -239,13 +339,18 @@ sadi_status upload_desc(sadi_batch* b, Group& g, bool scratch, const std::vector
 sadi_status set_scalars(sadi_batch* b, Group& g, bool first) {
   std::vector<sadi::BatchInst> h(g.members.size());
   SADI_HIP(hipMemcpy(h.data(), g.d_inst, sizeof(sadi::BatchInst) * h.size(), hipMemcpyDeviceToHost));
-  for (size_t k = 0; k < g.members.size(); ++k) h[k].sc = scalars(b->ctx[g.members[k]], first);
+  for (size_t k = 0; k < g.members.size(); ++k) {
+    h[k].sc = scalars(b->ctx[g.members[k]], first);
+    b->h_all[g.members[k]].sc = h[k].sc;
+  }
   SADI_HIP(hipMemcpy(g.d_inst, h.data(), sizeof(sadi::BatchInst) * h.size(), hipMemcpyHostToDevice));
   return SADI_OK;
 }
 
 void destroy_batch(sadi_batch* b) {
   b->drop_graph();
+  for (int p = 0; p < 3; ++p)
+    if (b->d_items[p]) (void)hipFree(b->d_items[p]);
   for (void* p : b->allocs) (void)hipFree(p);
   for (sadi_ctx* c : b->ctx)
     if (c) (void)sadi_destroy(c);
@@ -325,6 +430,14 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
       b->groups[it->second].members.push_back(i);
     }
   }
+  {
+    sadi_status st;
+    if ((st = b->alloc((void**)&b->d_all, sizeof(sadi::BatchInst) * count)) != SADI_OK ||
+        (st = b->alloc((void**)&b->d_all_scratch, sizeof(sadi::BatchInst) * count)) != SADI_OK)
+      return bail(st);
+    b->h_all.assign(count, sadi::BatchInst{});
+    b->h_all_scratch.assign(count, sadi::BatchInst{});
+  }
   for (Group& g : b->groups) {
     const size_t cnt = g.members.size();
     sadi_status st;
@@ -380,6 +493,9 @@ sadi_status sadi_batch_bind(sadi_batch* b, double* const* u_prev, double* const*
     sadi_status st = upload_desc(b, g, false, s0, s1);
     if (st != SADI_OK) return st;
   }
+  sadi_status st = upload_all(b, false);
+  if (st == SADI_OK) st = build_worklists(b);
+  if (st != SADI_OK) return st;
   b->drop_graph();
   b->bound = true;
   return SADI_OK;
@@ -400,6 +516,7 @@ sadi_status sadi_batch_first_step(sadi_batch* b) {
     sadi_status s2 = set_scalars(b, g, false);
     if (st == SADI_OK) st = s2;
   }
+  if (st == SADI_OK) st = upload_all(b, false);
   return st;
 }
 
@@ -426,7 +543,7 @@ sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path) {
       return fail(SADI_E_UNSUPPORTED, "no explicit inverse for N = " + std::to_string(n) + " (above dense_max_n)");
     g.path = path;
     b->drop_graph();
-    return SADI_OK;
+    return b->bound ? build_worklists(b) : SADI_OK;
   }
   return fail(SADI_E_INVALID, "no instance with N = " + std::to_string(n));
 }
@@ -474,6 +591,13 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
     return v;
   }();
   sadi_status st = SADI_OK;
+  const int saved_schedule = b->schedule;
+  b->schedule = 0;   // groups timed alone launch separately
+  if ((st = build_worklists(b)) != SADI_OK || (st = upload_all(b, true)) != SADI_OK) {
+    b->schedule = saved_schedule;
+    cleanup();
+    return st;
+  }
   // time each group alone: the other groups are skipped by moving them out temporarily
   std::vector<Group> all;
   all.swap(b->groups);
@@ -502,12 +626,49 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
       g.path = (g.ms[SADI_PATH_DENSE] >= 0.0 && g.ms[SADI_PATH_DENSE] < g.ms[SADI_PATH_FFT_GS]) ? SADI_PATH_DENSE
                                                                                                  : SADI_PATH_FFT_GS;
   }
+  // then the schedule of the whole step with those paths: every group on its own, or the
+  // FFT groups up to kWorkListMaxM sharing one launch per phase
+  b->schedule = saved_schedule;
+  for (int sched = 0; sched < 2 && st == SADI_OK; ++sched) {
+    b->schedule = sched;
+    if ((st = build_worklists(b)) != SADI_OK) break;
+    if ((st = batch_run(b, true, 2, false)) != SADI_OK) break;
+    (void)hipEventRecord(e0, b->stream);
+    st = batch_run(b, true, steps, false);
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) st = fail(SADI_E_DEVICE, "tuning run");
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    b->ms_schedule[sched] = ms / steps;
+  }
+  if (st == SADI_OK) b->schedule = b->ms_schedule[1] <= b->ms_schedule[0] ? 1 : 0;
+  else b->schedule = saved_schedule;
+  {
+    const sadi_status s2 = build_worklists(b);
+    if (st == SADI_OK) st = s2;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(b->stream);
   cleanup();
   b->drop_graph();
   return st;
+}
+
+sadi_status sadi_batch_set_schedule(sadi_batch* b, int schedule) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (schedule != 0 && schedule != 1) return fail(SADI_E_INVALID, "schedule must be 0 or 1");
+  b->schedule = schedule;
+  b->drop_graph();
+  return b->bound ? build_worklists(b) : SADI_OK;
+}
+
+sadi_status sadi_batch_get_schedule(const sadi_batch* b, int* schedule, double* ms_groups, double* ms_lists) {
+  if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
+  if (schedule) *schedule = b->schedule;
+  if (ms_groups) *ms_groups = b->ms_schedule[0];
+  if (ms_lists) *ms_lists = b->ms_schedule[1];
+  return SADI_OK;
 }
 
 sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,

@@ -465,16 +465,15 @@ __device__ __forceinline__ void shift_odd_slots(VV* d, bool odd, std::integer_se
 // out = IFFT_P(Lambda[kx] o FFT_P(c)), first N rows.  The length-P transform is split
 // into its even and odd frequencies (two length-M transforms of c and W_P^y c), each
 // handled by its own line of the workgroup (lines 2g / 2g+1 for column group g).
+// grp: this workgroup's column group (< the number of groups); smem: ColConvCfg<M>::LDS_BYTES
+// bytes of LDS.
 template <int M>
 __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
-                 FFTTables<double> tab, const V* __restrict__ root2M, int ngroups) {
+                 FFTTables<double> tab, const V* __restrict__ root2M, int grp, unsigned char* smem) {
   using Cfg = ColConvCfg<M>;
   using L_t = typename Cfg::Line;
   constexpr int E = L_t::E, T = L_t::T;
   constexpr int CPW = Cfg::LPW / 2;  // columns per workgroup
-  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
-  const int grp = xcd_group(ngroups);
-  if (grp >= ngroups) return;
   const L_t L(threadIdx.x);
   const int col = grp * CPW + L.line / 2;
   const int odd = L.line & 1;
@@ -661,17 +660,17 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
   }
 }
 
+// rowblk: this workgroup's block of RowCfg<M>::LPW rows; smem: RowCfg<M>::LDS_BYTES bytes.
 template <int M, int MODE, int XS>
 __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
-                   StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
+                   StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M, int rowblk,
+                   unsigned char* smem) {
   using L_t = typename RowCfg<M>::Line;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
   const L_t L(threadIdx.x);
-  constexpr bool PAIRED = RowCfg<M>::LPW == 1;
-  const int y = (PAIRED ? paired_row_block() : (int)blockIdx.x) * RowCfg<M>::LPW + L.line;
-  if (PAIRED && y >= n) return;   // a whole workgroup past the last row
+  const int y = rowblk * RowCfg<M>::LPW + L.line;
+  if (RowCfg<M>::LPW == 1 && y >= n) return;   // a whole workgroup past the last row
   const bool live = y < n;
   const int yy = live ? y : 0;
   // MODE 3 / 4: as 0 / 1 but X = B (no line solve; the dense-inverse path follows)
@@ -805,17 +804,15 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
 // next step.  With `fwd` the same column is then transformed along its length, which is
 // the next step's row transform: its half spectrum goes to row c of S.  XS: X in paired
 // rows (single instances) or plain rows (batch members).
+// grp: this workgroup's group of ColGSCfg<M>::LPW columns; smem: ColGSCfg<M>::LDS_BYTES bytes.
 template <int M, int XS>
 __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
                                                  double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_,
                                                  FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M,
-                                                 int ngroups, int fwd) {
+                                                 int grp, int fwd, unsigned char* smem) {
   using Cfg = ColGSCfg<M>;
   using L_t = typename Cfg::Line;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
-  const int grp = xcd_group(ngroups);
-  if (grp >= ngroups) return;   // whole workgroup
   const L_t L(threadIdx.x);
   const int col = grp * Cfg::LPW + L.line;
   const bool live = col < n;
@@ -1007,13 +1004,25 @@ template <int M>
 __global__ void __launch_bounds__(ColConvCfg<M>::NT) SADI_OCC4
 cols_conv_kernel(V* __restrict__ S, int lds_, int n, const double* __restrict__ lam, int ldlam,
                  FFTTables<double> tab, const V* __restrict__ root2M, int ngroups) {
-  cols_conv_body<M>(S, lds_, n, lam, ldlam, tab, root2M, ngroups);
+  __shared__ __align__(16) unsigned char smem[ColConvCfg<M>::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;
+  cols_conv_body<M>(S, lds_, n, lam, ldlam, tab, root2M, grp, smem);
 }
 template <int M>
 __global__ void __launch_bounds__(ColConvCfg<M>::NT) SADI_OCC4
 cols_conv_batched(const BatchInst* __restrict__ bi, int lds_, int n, int ldlam, FFTTables<double> tab, int ngroups) {
+  __shared__ __align__(16) unsigned char smem[ColConvCfg<M>::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;
   const BatchInst& p = bi[blockIdx.y];
-  cols_conv_body<M>(p.S, lds_, n, p.lam2d, ldlam, tab, tab.root2M, ngroups);
+  cols_conv_body<M>(p.S, lds_, n, p.lam2d, ldlam, tab, tab.root2M, grp, smem);
+}
+
+// blocks of rows_rhs_gs with one row per block are launched in paired order (multiple of 16)
+template <int M>
+__device__ __forceinline__ int rhs_row_block() {
+  return RowCfg<M>::LPW == 1 ? paired_row_block() : (int)blockIdx.x;
 }
 
 template <int M, int MODE, int XS>
@@ -1021,14 +1030,17 @@ __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
-  rows_rhs_gs_body<M, MODE, XS>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M);
+  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
+  rows_rhs_gs_body<M, MODE, XS>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M, rhs_row_block<M>(), smem);
 }
 template <int M, int MODE>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_batched(const BatchInst* __restrict__ bi, int iu, int lds_, int ldx, int n, FFTTables<double> tab) {
+  __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
-  rows_rhs_gs_body<M, MODE, 0>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M);
+  rows_rhs_gs_body<M, MODE, 0>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M,
+                               rhs_row_block<M>(), smem);
 }
 
 template <int M, int MODE, int XS>
@@ -1050,16 +1062,136 @@ __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_fwd_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur, double* __restrict__ prev_t,
                    int n, V* __restrict__ S, int lds_, FFTTables<double> tab, GSTables64 gs,
                    const V* __restrict__ root2M, int ngroups, int fwd) {
-  cols_gs_fwd_body<M, 1>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, ngroups, fwd);
+  __shared__ __align__(16) unsigned char smem[ColGSCfg<M>::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;   // whole workgroup
+  cols_gs_fwd_body<M, 1>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, grp, fwd, smem);
 }
 // batched: instance blockIdx.y; u[ic] = u^n in this step's layout, u[ip] = u^{n-1} transposed
 template <int M>
 __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_fwd_batched(const BatchInst* __restrict__ bi, int ic, int ip, int ldx, int lds_, int n,
                     FFTTables<double> tab, int ngroups) {
+  __shared__ __align__(16) unsigned char smem[ColGSCfg<M>::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;   // whole workgroup
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
-  cols_gs_fwd_body<M, 0>(p.X, ldx, p.u[ic], p.u[ip], n, p.S, lds_, tab, gs, tab.root2M, ngroups, 1);
+  cols_gs_fwd_body<M, 0>(p.X, ldx, p.u[ic], p.u[ip], n, p.S, lds_, tab, gs, tab.root2M, grp, 1, smem);
+}
+
+// ----------------------------------------------------------------------------------
+// Work lists: one launch per phase of the batched step for all instances with M <= 2048,
+// whatever their sizes.  Each workgroup takes (instance, block) from items[blockIdx.x] and
+// runs the single-instance body of that instance's M (a uniform branch); the launch uses the
+// largest LDS footprint of the bodies.  The host orders the list for the XCDs.
+#define SADI_WL_CASES(F) F(16) F(32) F(64) F(128) F(256) F(512) F(1024) F(2048)
+
+constexpr int cmax() { return 0; }
+template <typename... A> constexpr int cmax(int a, A... b) {
+  const int r = cmax(b...);
+  return a > r ? a : r;
+}
+#define SADI_WL_LDS(C, MM) , C<MM>::LDS_BYTES
+#define SADI_WL_CONV_LDS(MM) SADI_WL_LDS(ColConvCfg, MM)
+#define SADI_WL_ROW_LDS(MM) SADI_WL_LDS(RowCfg, MM)
+#define SADI_WL_GS_LDS(MM) SADI_WL_LDS(ColGSCfg, MM)
+constexpr int kWlConvLds = cmax(0 SADI_WL_CASES(SADI_WL_CONV_LDS));
+constexpr int kWlRowLds = cmax(0 SADI_WL_CASES(SADI_WL_ROW_LDS));
+constexpr int kWlGsLds = cmax(0 SADI_WL_CASES(SADI_WL_GS_LDS));
+constexpr int kWlConvNT = 256, kWlRowNT = 128, kWlGsNT = 256;
+#define SADI_WL_CHECK(MM)                                                                   \
+  static_assert(ColConvCfg<MM>::NT == kWlConvNT && RowCfg<MM>::NT == kWlRowNT &&            \
+                    ColGSCfg<MM>::NT == kWlGsNT,                                            \
+                "work-list phases need one workgroup size for every M");
+SADI_WL_CASES(SADI_WL_CHECK)
+
+__global__ void __launch_bounds__(kWlConvNT) SADI_OCC4
+cols_conv_worklist(const BatchInst* __restrict__ bi, const WorkItem* __restrict__ items) {
+  __shared__ __align__(16) unsigned char smem[kWlConvLds];
+  const WorkItem w = items[blockIdx.x];
+  if (w.inst < 0) return;
+  const BatchInst& p = bi[w.inst];
+  switch (p.m) {
+#define SADI_WL_CONV(MM)                                                                          \
+  case MM:                                                                                        \
+    cols_conv_body<MM>(p.S, p.lds, p.n, p.lam2d, p.ldlam, p.tab, p.tab.root2M, w.blk, smem);    \
+    break;
+    SADI_WL_CASES(SADI_WL_CONV)
+#undef SADI_WL_CONV
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(kWlRowNT) SADI_OCC4
+rows_rhs_gs_worklist(const BatchInst* __restrict__ bi, const WorkItem* __restrict__ items, int iu) {
+  __shared__ __align__(16) unsigned char smem[kWlRowLds];
+  const WorkItem w = items[blockIdx.x];
+  if (w.inst < 0) return;
+  const BatchInst& p = bi[w.inst];
+  const GSTables64 gs{p.tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
+  switch (p.m) {
+#define SADI_WL_ROW(MM)                                                                              \
+  case MM:                                                                                           \
+    rows_rhs_gs_body<MM, 0, 0>(p.S, p.lds, p.u[iu], p.n, p.phi2, p.X, p.ldx, p.n, p.sc, p.tab, gs,   \
+                               p.tab.root2M, w.blk, smem);                                           \
+    break;
+    SADI_WL_CASES(SADI_WL_ROW)
+#undef SADI_WL_ROW
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(kWlGsNT) SADI_OCC4
+cols_gs_fwd_worklist(const BatchInst* __restrict__ bi, const WorkItem* __restrict__ items, int ic, int ip) {
+  __shared__ __align__(16) unsigned char smem[kWlGsLds];
+  const WorkItem w = items[blockIdx.x];
+  if (w.inst < 0) return;
+  const BatchInst& p = bi[w.inst];
+  const GSTables64 gs{p.tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
+  switch (p.m) {
+#define SADI_WL_GS(MM)                                                                              \
+  case MM:                                                                                          \
+    cols_gs_fwd_body<MM, 0>(p.X, p.ldx, p.u[ic], p.u[ip], p.n, p.S, p.lds, p.tab, gs, p.tab.root2M, \
+                            w.blk, 1, smem);                                                        \
+    break;
+    SADI_WL_CASES(SADI_WL_GS)
+#undef SADI_WL_GS
+    default: break;
+  }
+}
+
+void worklist_shape(int m, int n, int blocks[3], double cost[3]) {
+  blocks[0] = blocks[1] = blocks[2] = 0;
+  cost[0] = cost[1] = cost[2] = 0.0;
+  switch (m) {
+#define SADI_WL_SHAPE(MM)                                                                     \
+  case MM: {                                                                                  \
+    constexpr int cpw = ColConvCfg<MM>::LPW / 2;                                              \
+    const double ml = (double)MM * __builtin_ctz(MM);                                         \
+    blocks[0] = (MM + 1 + cpw - 1) / cpw;                                                     \
+    blocks[1] = (n + RowCfg<MM>::LPW - 1) / RowCfg<MM>::LPW;                                  \
+    blocks[2] = (n + ColGSCfg<MM>::LPW - 1) / ColGSCfg<MM>::LPW;                              \
+    cost[0] = ColConvCfg<MM>::LPW * ml;                                                       \
+    cost[1] = RowCfg<MM>::LPW * ml;                                                           \
+    cost[2] = ColGSCfg<MM>::LPW * ml;                                                         \
+    break;                                                                                    \
+  }
+    SADI_WL_CASES(SADI_WL_SHAPE)
+#undef SADI_WL_SHAPE
+    default: break;
+  }
+}
+
+void launch_worklist(int phase, const BatchInst* bi, const WorkItem* items, int nitems, int iu, int ip,
+                     hipStream_t st) {
+  if (nitems <= 0) return;
+  if (phase == 0)
+    hipLaunchKernelGGL(cols_conv_worklist, dim3(nitems), dim3(kWlConvNT), 0, st, bi, items);
+  else if (phase == 1)
+    hipLaunchKernelGGL(rows_rhs_gs_worklist, dim3(nitems), dim3(kWlRowNT), 0, st, bi, items, iu);
+  else
+    hipLaunchKernelGGL(cols_gs_fwd_worklist, dim3(nitems), dim3(kWlGsNT), 0, st, bi, items, iu, ip);
 }
 
 // batched update, instance blockIdx.z, row blockIdx.y:

@@ -156,7 +156,28 @@ struct BatchInst {
   const double* f;
   int r;                    // M - N (the same for every instance of a launch)
   StepScalars sc;           // sigma, gamma carry this instance's kappa, h^-alpha, tau
+  // for launches that mix instances of different sizes (work lists): this instance's grid,
+  // line length, pitches of S (complex), X (doubles) and Lambda, and its line tables
+  int n, m, lds, ldx, ldlam;
+  FFTTables<double> tab;
 };
+
+// One workgroup's share of a work-list launch: instance `inst` of the descriptor array and
+// its block `blk` in the single-instance numbering of that phase; inst < 0: nothing to do.
+struct WorkItem {
+  int inst;
+  int blk;
+};
+// Work lists cover line lengths M <= kWorkListMaxM (their workgroup size is the same for all).
+constexpr int kWorkListMaxM = 2048;
+// Blocks of one instance in each phase of the batched step (0: column convolution,
+// 1: row pass with the x-sweep, 2: y-sweep with the next row transform) and a relative cost
+// per block (lines x M log2 M) for balancing.
+void worklist_shape(int m, int n, int blocks[3], double cost[3]);
+// One launch of phase `phase` over the work list (nitems entries).  iu: the state buffer the
+// step advances (phase 1, 2); ip: the other one (phase 2).
+void launch_worklist(int phase, const BatchInst* bi, const WorkItem* items, int nitems, int iu, int ip,
+                     hipStream_t st);
 
 // Dense FP64 products on the matrix cores: C = alpha A B + beta C (k may be 0: C = beta C).
 // C(i, j) at C[i ldc + j]; B(k, j) at B[k ldb + j]; A(i, k) at A[i lda + k] (a_rows) or at

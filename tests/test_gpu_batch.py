@@ -56,15 +56,17 @@ def reference(mb, nsteps):
     return _ref[key]
 
 
-def make_batch(path=None, graph=False):
+def make_batch(path=None, graph=False, schedule="work_lists"):
+    """path: one path for every group, or a dict N -> path."""
     from paper_2312_06206_amd import Batch
     _dev()
     ms = members()
     b = Batch([m.n for m in ms], [m.alpha for m in ms], [m.kappa for m in ms], TAU, dense_max_n=127)
     if path is not None:
         for n in sorted({m.n for m in ms}):
-            b.set_path(n, path)
+            b.set_path(n, path[n] if isinstance(path, dict) else path)
     b.set_graph(graph)
+    b.set_schedule(schedule)
     u0 = [to_dev(m.phi1()) for m in ms]
     u1 = [torch.zeros_like(t) for t in u0]
     p2 = [to_dev(0.3 * W.asymmetric_field(m.n, seed=m.n)) for m in ms]
@@ -72,10 +74,19 @@ def make_batch(path=None, graph=False):
     return b, ms, u0, u1
 
 
-@pytest.mark.parametrize("path,graph", [("fft_gs", False), ("fft_gs", True), ("dense", False), ("dense", True)])
-def test_batch_run_matches_oracle(path, graph):
-    _say(f"batch path={path} graph={graph}")
-    b, ms, u0, u1 = make_batch(path, graph)
+MIXED = {15: "dense", 31: "fft_gs", 63: "dense", 127: "fft_gs"}
+
+
+@pytest.mark.parametrize("path,graph,schedule", [("fft_gs", False, "work_lists"), ("fft_gs", True, "work_lists"),
+                                                 ("fft_gs", False, "groups"), ("fft_gs", True, "groups"),
+                                                 ("dense", False, "work_lists"), ("dense", True, "groups"),
+                                                 ("mixed", False, "work_lists"), ("mixed", True, "work_lists")])
+def test_batch_run_matches_oracle(path, graph, schedule):
+    """Both line-sweep paths (and a mix of them across groups), both launch schedules (the
+    FFT groups in shared work-list launches, or every group on its own), with and without
+    graph replay."""
+    _say(f"batch path={path} graph={graph} schedule={schedule}")
+    b, ms, u0, u1 = make_batch(MIXED if path == "mixed" else path, graph, schedule)
     with b:
         b.first_step()
         b.run(6)                      # steps 2..7
@@ -117,23 +128,28 @@ def test_batch_tune_keeps_state():
         for g in groups:
             assert g["ms_fft_gs"] > 0 and g["ms_dense"] > 0
             assert g["path"] == ("dense" if g["ms_dense"] < g["ms_fft_gs"] else "fft_gs")
+        sched, ms_groups, ms_lists = b.schedule()
+        assert ms_groups > 0 and ms_lists > 0
+        assert sched == ("work_lists" if ms_lists <= ms_groups else "groups")
         b.run(3)
         for k, m in enumerate(ms):
             assert rel(from_dev(u1[k]), reference(m, 4)[1]) < 1e-11
 
 
-def test_batch_at_the_benchmark_sizes():
+@pytest.mark.parametrize("schedule", ["work_lists", "groups"])
+def test_batch_at_the_benchmark_sizes(schedule):
     """Members drawn from the batched workload's sizes (N in {255, 511, 1023}, alpha and
     kappa from its distributions): the line-sweep path with graph replay, the start-up
     step and four steps against the oracle's runs."""
     from paper_2312_06206_amd import Batch
     _dev()
     ms = W.batch_members(4, seed=0, n_choices=(255, 511, 1023))   # N = 1023, 511, 1023, 255
-    _say(f"batch at benchmark sizes: {[m.n for m in ms]}")
+    _say(f"batch at benchmark sizes: {[m.n for m in ms]} schedule={schedule}")
     b = Batch([m.n for m in ms], [m.alpha for m in ms], [m.kappa for m in ms], TAU)
     for n in sorted({m.n for m in ms}):
         b.set_path(n, "fft_gs")
     b.set_graph(True)
+    b.set_schedule(schedule)
     u0 = [to_dev(m.phi1()) for m in ms]
     u1 = [torch.zeros_like(t) for t in u0]
     p2 = [to_dev(0.3 * W.asymmetric_field(m.n, seed=m.n)) for m in ms]
