@@ -180,6 +180,14 @@ sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out);
 sadi_status sadi_host_line_generator(double alpha, double kappa, int n, double tau, const double* domain,
                                      double* out);
 
+/* Node rows of the quadrature that gives a_ij (the subordination integral above, on
+ * nodes t_q equally spaced in log t): *nodes receives their number, x (if not NULL) the
+ * arguments x_q = 2 t_q, and rows (if not NULL, nodes x nrows values) e^{-x_q} I_k(x_q) at
+ * rows[q * nrows + k] for k < nrows <= 4096.  fp64 = 0: the host's extended-precision (long
+ * double) recurrence; fp64 = 1: the double-double float64 recurrence that builds the table
+ * on the GPU, run here on the host (the two are compared in the tests).  Host pointers. */
+sadi_status sadi_host_quadrature_rows(int nrows, int fp64, int* nodes, double* x, double* rows);
+
 /* Reverse-mode (adjoint) step, for gradients of a scalar J(u^K) with respect to phi1 and
  * kappa through the delta form above.  With J_n = H^-1 (-c kappa L_h + c diag g'(u^n)) H^-1
  * the Jacobian of the increment (c = tau^2, or tau^2/2 for the start-up step; H, L_h
@@ -261,14 +269,17 @@ sadi_status sadi_batch_set_schedule(sadi_batch* b, int schedule);
 sadi_status sadi_batch_get_schedule(const sadi_batch* b, int* schedule, double* ms_groups, double* ms_lists);
 
 /* Autotuner: for every group, time `steps` steps of each available path on zero scratch
- * state (the bound state is not touched) and keep the faster path; then time the whole step
- * under both schedules with those paths and keep the faster schedule.  Host-synchronous. */
+ * state (the bound state is not touched) -- the dense path with both tile shapes of its
+ * products (64 x 64 and 32 x 32 blocks of the result per workgroup) -- and keep the fastest;
+ * then time the whole step under both schedules with those paths and keep the faster
+ * schedule.  Host-synchronous. */
 sadi_status sadi_batch_tune(sadi_batch* b, int steps);
 
-/* Group `index` (0 <= index < groups): its N, member count, current path and the tuned
- * milliseconds per step of each path (-1 if not timed). */
+/* Group `index` (0 <= index < groups): its N, member count, current path, the tuned
+ * milliseconds per step of each path (-1 if not timed) and the tile of the dense products
+ * (64 or 32; 0: chosen by the number of tiles).  Any output pointer may be NULL. */
 sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,
-                                 double* ms_dense);
+                                 double* ms_dense, int* dense_tile);
 
 /* Instance and group counts, device bytes held by the batch. */
 sadi_status sadi_batch_get_info(const sadi_batch* b, int* count, int* groups, long long* bytes);

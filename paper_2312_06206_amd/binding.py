@@ -61,6 +61,7 @@ def load_library() -> ctypes.CDLL:
         "sadi_host_riesz_coeffs": (I, [D, I, DP]),
         "sadi_host_laplacian_coeffs": (I, [D, I, DP]),
         "sadi_host_line_generator": (I, [D, D, I, D, DP, DP]),
+        "sadi_host_quadrature_rows": (I, [I, I, P(I), DP, DP]),
         "sadi_adjoint_step": (I, [VP, I, VP, VP, VP, VP, VP, VP, VP]),
         "sadi_batch_create": (I, [I, P(I), DP, DP, D, DP, I, P(VP)]),
         "sadi_batch_bind": (I, [VP, P(VP), P(VP), P(VP)]),
@@ -71,7 +72,7 @@ def load_library() -> ctypes.CDLL:
         "sadi_batch_tune": (I, [VP, I]),
         "sadi_batch_set_schedule": (I, [VP, I]),
         "sadi_batch_get_schedule": (I, [VP, P(I), DP, DP]),
-        "sadi_batch_get_group": (I, [VP, I, P(I), P(I), P(I), DP, DP]),
+        "sadi_batch_get_group": (I, [VP, I, P(I), P(I), P(I), DP, DP, P(I)]),
         "sadi_batch_get_info": (I, [VP, P(I), P(I), P(ctypes.c_longlong)]),
         "sadi_batch_synchronize": (I, [VP]),
         "sadi_batch_destroy": (I, [VP]),
@@ -113,6 +114,19 @@ def host_line_generator(alpha, kappa, n, tau, domain=(-1.0, 1.0)) -> np.ndarray:
     dom = np.asarray(domain, dtype=np.float64)
     _check(load_library().sadi_host_line_generator(alpha, kappa, n, tau, _dptr(dom), _dptr(out)))
     return out
+
+
+def host_quadrature_rows(nrows: int, fp64: bool = False):
+    """(x, rows): the a_ij quadrature's node arguments x_q and e^{-x_q} I_k(x_q) for k < nrows,
+    shape (nodes, nrows); fp64 selects the double-double float64 recurrence the GPU table is
+    built with (run on the host), else the host's long double one."""
+    lib = load_library()
+    nq = ctypes.c_int()
+    _check(lib.sadi_host_quadrature_rows(int(nrows), int(bool(fp64)), ctypes.byref(nq), None, None))
+    x = np.empty(nq.value)
+    rows = np.empty((nq.value, nrows))
+    _check(lib.sadi_host_quadrature_rows(int(nrows), int(bool(fp64)), ctypes.byref(nq), _dptr(x), _dptr(rows)))
+    return x, rows
 
 
 # ---- device solver ---------------------------------------------------------------
@@ -353,12 +367,12 @@ class Batch:
         out = []
         names = {v: k for k, v in PATHS.items()}
         for i in range(ng.value):
-            n, mem, path = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            n, mem, path, tile = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
             mf, md = ctypes.c_double(), ctypes.c_double()
             _check(lib.sadi_batch_get_group(self._h, i, ctypes.byref(n), ctypes.byref(mem), ctypes.byref(path),
-                                            ctypes.byref(mf), ctypes.byref(md)))
+                                            ctypes.byref(mf), ctypes.byref(md), ctypes.byref(tile)))
             out.append({"n": n.value, "members": mem.value, "path": names[path.value],
-                        "ms_fft_gs": mf.value, "ms_dense": md.value})
+                        "ms_fft_gs": mf.value, "ms_dense": md.value, "dense_tile": tile.value})
         return out
 
     def device_bytes(self) -> int:

@@ -29,6 +29,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 SOURCES = [
     ("kernels.hip", "hip"),
     ("gemm.hip", "hip"),
+    ("setup_device.hip", "hip"),
     ("sadi.cpp", "hip"),
     ("batch.cpp", "hip"),
     ("setup_math.cpp", "c++"),

@@ -26,6 +26,7 @@ struct Group {
   sadi::BatchInst* d_scratch_inst = nullptr;  // same, state in scratch buffers (timing)
   int path = SADI_PATH_FFT_GS;
   double ms[2] = {-1.0, -1.0};                // timed ms per step for each path
+  int dense_tile = 0;                         // tile of the dense products (0: by tile count)
   // dense path: H^-1 per member (rows H^-1 e_k) and the pointer triples of the two
   // products per member: T = X H^-1 into the spectrum buffer S (as real), then X = H^-1 T
   std::vector<double*> hinv;
@@ -122,8 +123,10 @@ template <int M> struct BColsGS {
 sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
   const sadi_ctx* c = b->ctx[g.members[0]];
   const int n = g.n, cnt = (int)g.members.size();
-  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod1, cnt, true, c->ldX, n, c->ldX, 1.0, 0.0, b->stream);
-  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod2, cnt, false, n, c->ldX, c->ldX, 1.0, 0.0, b->stream);
+  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod1, cnt, true, c->ldX, n, c->ldX, 1.0, 0.0, b->stream,
+                     g.dense_tile);
+  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod2, cnt, false, n, c->ldX, c->ldX, 1.0, 0.0, b->stream,
+                     g.dense_tile);
   return check_launch();
 }
 
@@ -585,6 +588,7 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
     cleanup();
     return fail(SADI_E_DEVICE, "hipEventCreate");
   }
+  for (Group& g : b->groups) g.ms[0] = g.ms[1] = -1.0;
   const std::vector<int> saved = [&] {
     std::vector<int> v;
     for (Group& g : b->groups) v.push_back(g.path);
@@ -603,9 +607,13 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
   all.swap(b->groups);
   for (size_t gi = 0; gi < all.size() && st == SADI_OK; ++gi) {
     b->groups.assign(1, all[gi]);
-    for (int path = 0; path < 2 && st == SADI_OK; ++path) {
+    // the Gohberg-Semencul path, then the dense path with each tile shape of its products
+    const int variants[3][2] = {{SADI_PATH_FFT_GS, 0}, {SADI_PATH_DENSE, 64}, {SADI_PATH_DENSE, 32}};
+    for (int v = 0; v < 3 && st == SADI_OK; ++v) {
+      const int path = variants[v][0];
       if (path == SADI_PATH_DENSE && all[gi].hinv.empty()) continue;
       b->groups[0].path = path;
+      b->groups[0].dense_tile = variants[v][1];
       st = batch_run(b, true, 2, false);   // warm-up
       if (st != SADI_OK) break;
       (void)hipEventRecord(e0, b->stream);
@@ -614,7 +622,11 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
       if (hipEventSynchronize(e1) != hipSuccess) st = fail(SADI_E_DEVICE, "tuning run");
       float ms = 0.0f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      all[gi].ms[path] = ms / steps;
+      const double per = ms / steps;
+      if (all[gi].ms[path] < 0.0 || per < all[gi].ms[path]) {
+        all[gi].ms[path] = per;
+        if (path == SADI_PATH_DENSE) all[gi].dense_tile = variants[v][1];
+      }
     }
     b->groups.clear();
   }
@@ -672,7 +684,7 @@ sadi_status sadi_batch_get_schedule(const sadi_batch* b, int* schedule, double* 
 }
 
 sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,
-                                 double* ms_dense) {
+                                 double* ms_dense, int* dense_tile) {
   if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
   if (index < 0 || index >= (int)b->groups.size()) return fail(SADI_E_INVALID, "group index out of range");
   const Group& g = b->groups[index];
@@ -681,6 +693,7 @@ sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* me
   if (path) *path = g.path;
   if (ms_fft) *ms_fft = g.ms[SADI_PATH_FFT_GS];
   if (ms_dense) *ms_dense = g.ms[SADI_PATH_DENSE];
+  if (dense_tile) *dense_tile = g.dense_tile;
   return SADI_OK;
 }
 

@@ -116,6 +116,13 @@ struct sadi_ctx {
   }
 };
 
+namespace sadi {
+// The node rows ive(k, x_q) of the a_ij quadrature on the current device (setup_device.hip):
+// rows[q * ld + k] for k < ld, and their first kLapLowOrders orders on the host,
+// low[q * kLapLowOrders + k].  Built on first use per device, kept until the process ends.
+sadi_status quadrature_table(const double** rows, int* ld, const double** low);
+}  // namespace sadi
+
 namespace sadi_impl {
 
 inline bool ctx_ok(const sadi_ctx* c) { return c != nullptr && c->magic == 0x5AD1; }

@@ -1,11 +1,12 @@
 // Dense FP64 matrix products on the matrix cores of gfx950 (v_mfma_f64_16x16x4_f64).
 //
-// C = alpha A B + beta C, C row-major (C(i, j) at C[i ldc + j]), B with contiguous rows
-// (B(k, j) at B[k ldb + j]), A either with contiguous rows (AK: A(i, k) at A[i lda + k])
-// or contiguous columns (A(i, k) at A[k lda + i]).  Blocks of 256 threads compute 64 x 64
-// tiles of C: four waves in a 2 x 2 arrangement, each wave a 32 x 32 quarter as 2 x 2 MFMA
-// tiles of 16 x 16.  K advances in slices of 16 staged through LDS, double buffered: the
-// global loads of slice s + 1 are in flight while the matrix cores work on slice s.
+// C = alpha A diag(s) B + beta C (s optional), C row-major (C(i, j) at C[i ldc + j]), B with
+// contiguous rows (B(k, j) at B[k ldb + j]), A either with contiguous rows (AK: A(i, k) at A[i lda + k])
+// or contiguous columns (A(i, k) at A[k lda + i]).  A block of WM x WN waves computes a
+// (32 WM) x (32 WN) tile of C, each wave a 32 x 32 part as 2 x 2 MFMA tiles of 16 x 16; two
+// shapes are built, 64 x 64 (four waves) and 32 x 32 (one wave, for products with few
+// tiles).  K advances in slices of 16 staged through LDS, double buffered: the global loads
+// of slice s + 1 are in flight while the matrix cores work on slice s.
 // Batches: blockIdx.z indexes an array of (A, B, C) pointer triples; without the array
 // the single triple passed by value is used.
 //
@@ -20,54 +21,60 @@ namespace sadi {
 
 namespace {
 
-constexpr int kBM = 64, kBN = 64, kBK = 16;
+constexpr int kBK = 16;
 constexpr int kPad = 1;   // LDS row padding (doubles)
 
 using acc4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 
-// A slice (kBM rows x kBK columns of op(A)) and a B slice (kBK x kBN) staged in registers,
-// 4 values of each per thread.  Loads run along the contiguous direction: AK: 16 lanes per
-// row of A (128 bytes), rows t / 16 + 16 q; otherwise 64 lanes along a column of A (512
-// bytes), columns t / 64 + 4 q.  B: 64 lanes along a row, rows t / 64 + 4 q.
-template <bool AK>
+// Slices of A (BM x 16 of op(A)) and B (16 x BN) staged in registers.  Loads run along the
+// contiguous direction: AK: 16 lanes per row of A (128 bytes); otherwise BM lanes along a
+// column of A; B: BN lanes along a row.
+template <bool AK, int BM, int BN, int NT>
 struct Stage {
-  double a[4], b[4];
+  static constexpr int QA = BM * kBK / NT, QB = BN * kBK / NT;
+  double a[QA], b[QB];
 
   __device__ __forceinline__ void load(const double* __restrict__ A, long lda, const double* __restrict__ B,
-                                       long ldb, int m, int n, int k, int i0, int j0, int k0, int t) {
+                                       long ldb, const double* __restrict__ bscale, int m, int n, int k, int i0,
+                                       int j0, int k0, int t) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = AK ? i0 + (t >> 4) + 16 * q : i0 + (t & 63);
-      const int kk = AK ? k0 + (t & 15) : k0 + (t >> 6) + 4 * q;
-      const bool in = i < m && kk < k;
-      a[q] = in ? (AK ? A[(long)i * lda + kk] : A[(long)kk * lda + i]) : 0.0;
-      const int kb = k0 + (t >> 6) + 4 * q, j = j0 + (t & 63);
+    for (int q = 0; q < QA; ++q) {
+      const int i = AK ? i0 + t / 16 + (NT / 16) * q : i0 + t % BM;
+      const int kk = AK ? k0 + t % 16 : k0 + t / BM + (NT / BM) * q;
+      a[q] = (i < m && kk < k) ? (AK ? A[(long)i * lda + kk] : A[(long)kk * lda + i]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int kb = k0 + t / BN + (NT / BN) * q, j = j0 + t % BN;
       b[q] = (kb < k && j < n) ? B[(long)kb * ldb + j] : 0.0;
+      if (bscale && kb < k) b[q] *= bscale[kb];
     }
   }
 
   // into LDS, both k-major: As[kk][i], Bs[kk][j]
-  __device__ __forceinline__ void store(double (*As)[kBM + kPad], double (*Bs)[kBN + kPad], int t) const {
+  __device__ __forceinline__ void store(double (*As)[BM + kPad], double (*Bs)[BN + kPad], int t) const {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if constexpr (AK) As[t & 15][(t >> 4) + 16 * q] = a[q];
-      else As[(t >> 6) + 4 * q][t & 63] = a[q];
-      Bs[(t >> 6) + 4 * q][t & 63] = b[q];
+    for (int q = 0; q < QA; ++q) {
+      if constexpr (AK) As[t % 16][t / 16 + (NT / 16) * q] = a[q];
+      else As[t / BM + (NT / BM) * q][t % BM] = a[q];
     }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Bs[t / BN + (NT / BN) * q][t % BN] = b[q];
   }
 };
 
-template <bool AK>
-__global__ void __launch_bounds__(256)
+template <bool AK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
 dgemm_mfma_kernel(int m, int n, int k, GemmPtrs single, const GemmPtrs* __restrict__ batch, long lda, long ldb,
-                  long ldc, double alpha, double beta) {
-  __shared__ double As[2][kBK][kBM + kPad];
-  __shared__ double Bs[2][kBK][kBN + kPad];
+                  long ldc, double alpha, double beta, const double* __restrict__ bscale) {
+  constexpr int BM = 32 * WM, BN = 32 * WN, NT = 64 * WM * WN;
+  __shared__ double As[2][kBK][BM + kPad];
+  __shared__ double Bs[2][kBK][BN + kPad];
   const GemmPtrs p = batch ? batch[blockIdx.z] : single;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;      // the wave's 32 x 32 quarter
-  const int i0 = blockIdx.y * kBM, j0 = blockIdx.x * kBN;
+  const int wm = wave / WN, wn = wave % WN;     // the wave's 32 x 32 part
+  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
 
   acc4 acc[2][2];
 #pragma unroll
@@ -75,15 +82,15 @@ dgemm_mfma_kernel(int m, int n, int k, GemmPtrs single, const GemmPtrs* __restri
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = acc4{0.0, 0.0, 0.0, 0.0};
 
-  Stage<AK> st;
-  st.load(p.A, lda, p.B, ldb, m, n, k, i0, j0, 0, t);
+  Stage<AK, BM, BN, NT> st;
+  st.load(p.A, lda, p.B, ldb, bscale, m, n, k, i0, j0, 0, t);
   st.store(As[0], Bs[0], t);
   __syncthreads();
   const int nslices = (k + kBK - 1) / kBK;
   const int fr = lane & 15, fk = lane >> 4;     // fragment row / k of this lane
   for (int s = 0; s < nslices; ++s) {
     const int cur = s & 1;
-    if (s + 1 < nslices) st.load(p.A, lda, p.B, ldb, m, n, k, i0, j0, (s + 1) * kBK, t);
+    if (s + 1 < nslices) st.load(p.A, lda, p.B, ldb, bscale, m, n, k, i0, j0, (s + 1) * kBK, t);
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
       const double a0 = As[cur][kk + fk][wm * 32 + fr];
@@ -119,18 +126,35 @@ dgemm_mfma_kernel(int m, int n, int k, GemmPtrs single, const GemmPtrs* __restri
     }
 }
 
+template <int WM, int WN>
+void launch_shape(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* batch, int count, bool a_rows,
+                  long lda, long ldb, long ldc, double alpha, double beta, const double* bscale, hipStream_t st) {
+  const dim3 grid((n + 32 * WN - 1) / (32 * WN), (m + 32 * WM - 1) / (32 * WM), batch ? count : 1);
+  const dim3 blk(64 * WM * WN);
+  if (a_rows)
+    hipLaunchKernelGGL((dgemm_mfma_kernel<true, WM, WN>), grid, blk, 0, st, m, n, k, single, batch, lda, ldb, ldc,
+                       alpha, beta, bscale);
+  else
+    hipLaunchKernelGGL((dgemm_mfma_kernel<false, WM, WN>), grid, blk, 0, st, m, n, k, single, batch, lda, ldb, ldc,
+                       alpha, beta, bscale);
+}
+
 }  // namespace
 
 void launch_dgemm(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* batch, int count, bool a_rows,
-                  long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st) {
+                  long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st, int tile,
+                  const double* bscale) {
   if (m <= 0 || n <= 0 || count <= 0) return;
-  const dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, batch ? count : 1);
-  if (a_rows)
-    hipLaunchKernelGGL(dgemm_mfma_kernel<true>, grid, dim3(256), 0, st, m, n, k, single, batch, lda, ldb, ldc, alpha,
-                       beta);
+  const long batches = batch ? count : 1;
+  if (tile == 0) {
+    // 64 x 64 unless that leaves fewer than two blocks per CU of the 256
+    const long big = (long)((m + 63) / 64) * ((n + 63) / 64) * batches;
+    tile = big >= 512 ? 64 : 32;
+  }
+  if (tile == 64)
+    launch_shape<2, 2>(m, n, k, single, batch, count, a_rows, lda, ldb, ldc, alpha, beta, bscale, st);
   else
-    hipLaunchKernelGGL(dgemm_mfma_kernel<false>, grid, dim3(256), 0, st, m, n, k, single, batch, lda, ldb, ldc, alpha,
-                       beta);
+    launch_shape<1, 1>(m, n, k, single, batch, count, a_rows, lda, ldb, ldc, alpha, beta, bscale, st);
 }
 
 }  // namespace sadi

@@ -183,13 +183,16 @@ void launch_worklist(int phase, const BatchInst* bi, const WorkItem* items, int 
 // C(i, j) at C[i ldc + j]; B(k, j) at B[k ldb + j]; A(i, k) at A[i lda + k] (a_rows) or at
 // A[k lda + i].  batch: device array of count pointer triples (blockIdx.z), or null to use
 // `single`.  No element of C may also be an element of A or B (they may share a buffer).
+// tile: 64 or 32 (square tile of C per workgroup), 0 picks by the number of tiles.  bscale:
+// optional k-vector s, C = alpha A diag(s) B + beta C.
 struct GemmPtrs {
   const double* A;
   const double* B;
   double* C;
 };
 void launch_dgemm(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* batch, int count, bool a_rows,
-                  long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st);
+                  long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st, int tile = 0,
+                  const double* bscale = nullptr);
 
 // hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev),
 // hat in plain rows of pitch ldx

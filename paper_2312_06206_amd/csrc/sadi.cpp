@@ -237,10 +237,10 @@ sadi_status enqueue_step(sadi_ctx* c, int mode, const double* ucur, const double
   return check_launch();
 }
 
-// a2: the coefficient table a_ij (N x N), or empty with lf: its rank-k factors, multiplied
-// out on the device
+// a2: the coefficient table a_ij (N x N), or empty with ls: the alpha-dependent parts of its
+// quadrature, combined on the device with the node rows of quadrature_table
 sadi_status build_ctx(double alpha, double kappa, int n, double tau, const double* domain,
-                      const std::vector<double>& a1, const std::vector<double>& a2, const sadi::LapFactors* lf,
+                      const std::vector<double>& a1, const std::vector<double>& a2, const sadi::LapSetup* ls,
                       sadi_ctx** out) {
   sadi_ctx* c = new (std::nothrow) sadi_ctx();
   if (!c) return fail(SADI_E_NOMEM, "host allocation failed");
@@ -371,15 +371,17 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   if ((st = up(c->sig_e, hsig_e.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
   if ((st = up(c->sig_o, hsig_o.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
 
-  // ---- a_ij on the device (rank-k product on the matrix cores, then the exact corner) unless a table
-  // was given, and the eigenvalues of the block-circulant embedding of L_h with the row
-  // transform: two passes of even-extension DFTs (temporaries freed)
+  // ---- a_ij on the device unless a table was given: the quadrature over the nodes and the
+  // high tail as two matrix-core products, then the exact corner; then the eigenvalues of
+  // the block-circulant embedding of L_h with the row transform: two passes of
+  // even-extension DFTs (temporaries freed)
   {
     double* a2d = nullptr;
     double* gt = nullptr;
     double2* spec = nullptr;
-    double* fl = nullptr;
-    double* fr = nullptr;
+    double* fw = nullptr;
+    double* fa = nullptr;
+    double* fc = nullptr;
     auto tmp = [&](void** p, size_t bytes) -> sadi_status {
       hipError_t e = hipMalloc(p, bytes);
       if (e != hipSuccess) {
@@ -389,7 +391,7 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
       return SADI_OK;
     };
     auto drop = [&]() {
-      for (void* p : {(void*)a2d, (void*)gt, (void*)spec, (void*)fl, (void*)fr})
+      for (void* p : {(void*)a2d, (void*)gt, (void*)spec, (void*)fw, (void*)fa, (void*)fc})
         if (p) (void)hipFree(p);
     };
     const size_t nn = (size_t)n * n;
@@ -399,23 +401,33 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
       drop();
       return bail(st);
     }
-    if (lf) {
-      // a2d(i, j) = scale * sum_q L[q][i] R[q][j]: L, R are n x k column-major (rows of n)
-      const size_t fk = (size_t)lf->k * n;
-      if ((st = tmp((void**)&fl, sizeof(double) * fk)) != SADI_OK ||
-          (st = tmp((void**)&fr, sizeof(double) * fk)) != SADI_OK ||
-          (st = up(fl, lf->L.data(), sizeof(double) * fk)) != SADI_OK ||
-          (st = up(fr, lf->R.data(), sizeof(double) * fk)) != SADI_OK) {
+    if (ls) {
+      const double* rows = nullptr;
+      const double* low = nullptr;
+      int ldr = 0;
+      if ((st = sadi::quadrature_table(&rows, &ldr, &low)) != SADI_OK) {
         drop();
         return bail(st);
       }
-      // a2d[j n + i] = scale sum_q L[q][i] R[q][j]: row j of the product R^T L (matrix cores)
-      sadi::launch_dgemm(n, n, lf->k, sadi::GemmPtrs{fr, fl, a2d}, nullptr, 1, false, n, n, n, lf->scale, 0.0,
+      const size_t ft = (size_t)ls->ht * n;
+      if ((st = tmp((void**)&fw, sizeof(double) * ls->nq)) != SADI_OK ||
+          (st = tmp((void**)&fa, sizeof(double) * ft)) != SADI_OK ||
+          (st = tmp((void**)&fc, sizeof(double) * ft)) != SADI_OK ||
+          (st = up(fw, ls->w.data(), sizeof(double) * ls->nq)) != SADI_OK ||
+          (st = up(fa, ls->tail_a.data(), sizeof(double) * ft)) != SADI_OK ||
+          (st = up(fc, ls->tail_c.data(), sizeof(double) * ft)) != SADI_OK) {
+        drop();
+        return bail(st);
+      }
+      // a2d[j n + i] = scale (sum_q R[q][j] w_q R[q][i] + sum_p C_p(j) A_p(i)), R the node rows
+      sadi::launch_dgemm(n, n, ls->nq, sadi::GemmPtrs{rows, rows, a2d}, nullptr, 1, false, ldr, ldr, n, ls->scale,
+                         0.0, c->stream, 0, fw);
+      sadi::launch_dgemm(n, n, ls->ht, sadi::GemmPtrs{fc, fa, a2d}, nullptr, 1, false, n, n, n, ls->scale, 1.0,
                          c->stream);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess)
-        e = hipMemcpy2DAsync(a2d, sizeof(double) * n, lf->corner.data(), sizeof(double) * lf->nc,
-                             sizeof(double) * lf->nc, lf->nc, hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpy2DAsync(a2d, sizeof(double) * n, ls->corner.data(), sizeof(double) * ls->nc,
+                             sizeof(double) * ls->nc, ls->nc, hipMemcpyHostToDevice, c->stream);
       if (e != hipSuccess) {
         drop();
         return bail(fail(SADI_E_DEVICE, std::string("coefficient product: ") + hipGetErrorString(e)));
@@ -450,8 +462,13 @@ sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const doub
   if (st != SADI_OK) return st;
   try {
     const std::vector<double> a1 = sadi::riesz_coeffs(alpha, sadi::line_size(n));
-    const sadi::LapFactors lf = sadi::laplacian_factors(alpha, n, g_setup_threads);
-    return build_ctx(alpha, kappa, n, tau, domain, a1, {}, &lf, out);
+    const double* rows = nullptr;
+    const double* low = nullptr;
+    int ldr = 0;
+    st = sadi::quadrature_table(&rows, &ldr, &low);
+    if (st != SADI_OK) return st;
+    const sadi::LapSetup ls = sadi::laplacian_setup(alpha, n, low);
+    return build_ctx(alpha, kappa, n, tau, domain, a1, {}, &ls, out);
   } catch (const std::bad_alloc&) {
     return fail(SADI_E_NOMEM, "host allocation failed in setup");
   } catch (const std::exception& e) {

@@ -32,7 +32,6 @@ constexpr double kSHi = 42.0;
 constexpr double kXHankel = 1.0e8; // x = 2t above this: Hankel series for ive
 constexpr int kHankelTerms = 24;
 constexpr int kSeriesDeg = 40;
-constexpr int kLowOrders = 12;     // low-tail series needed only for i + j < this
 
 int worker_count(int requested) {
   if (requested > 0) return requested;
@@ -182,40 +181,38 @@ std::vector<double> riesz_coeffs(double alpha, int count) {
   return a;
 }
 
-LapFactors laplacian_factors(double alpha, int n, int nthreads) {
-  LapFactors f;
+int lap_node_count() { return (int)std::lround((kSHi - kSLo) / kStep) + 1; }
+
+double lap_node_x(int q) { return 2.0 * std::exp(kSLo + q * kStep); }
+
+LapSetup laplacian_setup(double alpha, int n, const double* ive_low) {
+  LapSetup f;
   if (n <= 0) return f;
   const long double beta = (long double)alpha / 2;
   const long double cb = beta / std::tgamma(1.0L - beta);
-  const int nq = (int)std::lround((kSHi - kSLo) / kStep) + 1;
-  const int nw = worker_count(nthreads);
-  const int HT = 16;   // Hankel terms of the high tail
+  const int nq = lap_node_count();
+  const int HT = kLapTailTerms;
   f.n = n;
-  f.k = nq + HT;
+  f.nq = nq;
+  f.ht = HT;
   f.scale = (double)(-cb);
-  f.L.assign((size_t)f.k * n, 0.0);
-  f.R.assign((size_t)f.k * n, 0.0);
+  f.w.resize(nq);
 
-  // node rows: L[q][k] = R[q][k] = sqrt(w_q) ive(k, 2 t_q), and the origin integrand
-  std::vector<long double> orig(nq);
-  parallel_for(nq, nw, [&](int q) {
-    const double s = kSLo + q * kStep;
-    const double t = std::exp(s);
-    double* row = &f.L[(size_t)q * n];
-    ive_all(2.0 * t, n, row);
-    const long double w = kStep * std::exp(-beta * s);
-    orig[q] = w * one_minus_ive0_sq(t, row[0]);
-    const double sw = (double)std::sqrt(w);
-    for (int k = 0; k < n; ++k) row[k] *= sw;
-    std::copy(row, row + n, &f.R[(size_t)q * n]);
-  });
+  // node weights (trapezoid step times t^-beta) and the origin integrand (1 - ive0^2) t^-beta
   long double acc0 = 0.0L;
-  for (int q = 0; q < nq; ++q) acc0 += orig[q];
+  for (int q = 0; q < nq; ++q) {
+    const double sq = kSLo + q * kStep;
+    const long double w = kStep * std::exp(-beta * sq);
+    f.w[q] = (double)w;
+    acc0 += w * one_minus_ive0_sq(std::exp(sq), ive_low[(size_t)q * kLapLowOrders]);
+  }
 
   // Hankel coefficients A_m(k) of ive(k, 2t) = (4 pi t)^-1/2 sum_m A_m(k) t^-m, for the high
-  // tail: rows nq + p hold L = A_p and R = C_p with C[p][j] = sum_r Wt[p][r] A_r(j), so that
-  // the high tail of (i, j) is sum_p A_p(i) C[p][j] (symmetric: Wt depends on p + r only)
-  double* A = &f.L[(size_t)nq * n];
+  // tail: rows p of tail_a hold A_p and of tail_c C_p with C[p][j] = sum_r Wt[p][r] A_r(j),
+  // so that the high tail of (i, j) is sum_p A_p(i) C[p][j] (Wt depends on p + r only)
+  f.tail_a.assign((size_t)HT * n, 0.0);
+  f.tail_c.assign((size_t)HT * n, 0.0);
+  double* A = f.tail_a.data();
   for (int k = 0; k < n; ++k) {
     const long double mu = 4.0L * k * k;
     long double term = 1.0L;
@@ -229,7 +226,7 @@ LapFactors laplacian_factors(double alpha, int n, int nthreads) {
   std::vector<long double> Wt(HT * HT, 0.0L);
   for (int p = 0; p < HT; ++p)
     for (int r = 0; p + r < HT; ++r) Wt[p * HT + r] = geom_tail(-(1.0L + beta + p + r), kSHi, +1) / (4.0L * pi);
-  double* Cht = &f.R[(size_t)nq * n];
+  double* Cht = f.tail_c.data();
   for (int p = 0; p < HT; ++p)
     for (int j = 0; j < n; ++j) {
       long double sacc = 0.0L;
@@ -237,17 +234,19 @@ LapFactors laplacian_factors(double alpha, int n, int nthreads) {
       Cht[(size_t)p * n + j] = (double)sacc;
     }
 
-  // corner i, j < nc: the factor product plus the low tail (small i + j) and the origin,
-  // whose integrand is (1 - ive0^2) t^-beta
-  const int nc = std::min(n, kLowOrders);
+  // corner i, j < nc: the factor product plus the low tail (small i + j) and the origin
+  const int nc = std::min(n, kLapLowOrders);
   f.nc = nc;
   f.corner.assign((size_t)nc * nc, 0.0);
   for (int i = 0; i < nc; ++i)
     for (int j = 0; j < nc; ++j) {
       long double acc = 0.0L;
-      for (int q = 0; q < f.k; ++q) acc += (long double)f.L[(size_t)q * n + i] * f.R[(size_t)q * n + j];
+      for (int q = 0; q < nq; ++q)
+        acc += (long double)f.w[q] * ive_low[(size_t)q * kLapLowOrders + i] * ive_low[(size_t)q * kLapLowOrders + j];
+      for (int p = 0; p < HT; ++p) acc += (long double)A[(size_t)p * n + i] * Cht[(size_t)p * n + j];
       long double v = -cb * acc;
-      if (i + j > 0 && i + j < kLowOrders) v += -cb * low_tail(series_product(4.0L, std::min(i, j), std::max(i, j)), beta, false);
+      if (i + j > 0 && i + j < kLapLowOrders)
+        v += -cb * low_tail(series_product(4.0L, std::min(i, j), std::max(i, j)), beta, false);
       f.corner[(size_t)j * nc + i] = (double)v;
     }
   {
@@ -261,6 +260,40 @@ LapFactors laplacian_factors(double alpha, int n, int nthreads) {
     acc0 += geom_tail(-beta, kSHi, +1) - hi00;
     f.corner[0] = (double)(cb * acc0);
   }
+  return f;
+}
+
+std::vector<double> ive_node_rows(int nrows, int nthreads) {
+  const int nq = lap_node_count();
+  std::vector<double> rows((size_t)nq * nrows);
+  parallel_for(nq, worker_count(nthreads), [&](int q) { ive_all(lap_node_x(q), nrows, &rows[(size_t)q * nrows]); });
+  return rows;
+}
+
+LapFactors laplacian_factors(double alpha, int n, int nthreads) {
+  LapFactors f;
+  if (n <= 0) return f;
+  const int nq = lap_node_count();
+  // node rows ive(k, 2 t_q), k < n, on the host (long double Miller recurrence)
+  const std::vector<double> rows = ive_node_rows(n, nthreads);
+  std::vector<double> low((size_t)nq * kLapLowOrders, 0.0);
+  for (int q = 0; q < nq; ++q)
+    for (int k = 0; k < std::min(n, kLapLowOrders); ++k) low[(size_t)q * kLapLowOrders + k] = rows[(size_t)q * n + k];
+  const LapSetup ls = laplacian_setup(alpha, n, low.data());
+  f.n = n;
+  f.k = nq + ls.ht;
+  f.nc = ls.nc;
+  f.scale = ls.scale;
+  f.corner = ls.corner;
+  f.L.assign((size_t)f.k * n, 0.0);
+  f.R.assign((size_t)f.k * n, 0.0);
+  // node rows: L[q][k] = R[q][k] = sqrt(w_q) ive(k, 2 t_q); then the high-tail rows
+  for (int q = 0; q < nq; ++q) {
+    const double sw = std::sqrt(ls.w[q]);
+    for (int k = 0; k < n; ++k) f.L[(size_t)q * n + k] = f.R[(size_t)q * n + k] = sw * rows[(size_t)q * n + k];
+  }
+  std::copy(ls.tail_a.begin(), ls.tail_a.end(), f.L.begin() + (size_t)nq * n);
+  std::copy(ls.tail_c.begin(), ls.tail_c.end(), f.R.begin() + (size_t)nq * n);
   return f;
 }
 

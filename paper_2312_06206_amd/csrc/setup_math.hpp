@@ -25,6 +25,25 @@ struct LapFactors {
 };
 LapFactors laplacian_factors(double alpha, int n, int nthreads = 0);
 
+// The same quadrature split by where its parts are computed.  The node rows ive(k, x_q),
+// x_q = 2 t_q (q < lap_node_count()), do not depend on alpha; everything else does and is
+// cheap: LapSetup holds the node weights w_q (a_ij gets w_q ive(i, x_q) ive(j, x_q) from node
+// q), the high-tail rows (a_ij gets sum_p tail_a[p][i] tail_c[p][j]), the overall factor
+// `scale`, and the exact corner i, j < nc.  ive_low: ive(k, x_q) for k < kLapLowOrders at
+// ive_low[q * kLapLowOrders + k].
+constexpr int kLapLowOrders = 12;   // low-tail series needed only for i + j < this
+constexpr int kLapTailTerms = 16;   // Hankel terms of the high tail
+struct LapSetup {
+  int n = 0, nq = 0, ht = 0, nc = 0;
+  double scale = 0.0;
+  std::vector<double> w, tail_a, tail_c, corner;
+};
+int lap_node_count();
+double lap_node_x(int q);
+LapSetup laplacian_setup(double alpha, int n, const double* ive_low);
+// ive(k, x_q) for k < nrows at every node (host, long double recurrence): [q * nrows + k]
+std::vector<double> ive_node_rows(int nrows, int nthreads = 0);
+
 // First column of T^-1 for the SPD Toeplitz T with first column t[0..m-1]
 // (Levinson-Durbin, extended precision).
 std::vector<long double> toeplitz_first_column_inverse(const std::vector<long double>& t);

@@ -548,3 +548,22 @@ def test_configured_run_1000_steps_fp32_unrefined():
     e = np.abs(got.ravel()[ref["idx"]] - ref["cur"]).max() / ref["full_max"][1]
     _say(f"  u^1000 vs oracle run: {e:.2e}")
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("n,alpha", [(255, 1.2), (1023, 1.8), (4095, 1.5)])
+def test_device_coefficients_match_host_tables(n, alpha):
+    """a_ij formed on the device (node rows from the GPU's double-double Miller recurrence,
+    weighted product on the matrix cores, exact corner from the host) against a context built
+    from the host set-up's own a_ij table (long double recurrence, host product): the BTTB
+    products of the two contexts agree to 2e-14 relative."""
+    from paper_2312_06206_amd import host_laplacian_coeffs, host_riesz_coeffs
+    _say(f"device a_ij vs host tables n={n} alpha={alpha}")
+    U = W.asymmetric_field(n, seed=13)
+    a1 = host_riesz_coeffs(alpha, n + 1)
+    a2 = host_laplacian_coeffs(alpha, n)
+    with solver(alpha, n, 1e-3) as s_dev, solver(alpha, n, 1e-3, a1=a1, a2=a2) as s_host:
+        got = from_dev(s_dev.apply_lh(to_dev(U)))
+        ref = from_dev(s_host.apply_lh(to_dev(U)))
+    err = rel(got, ref)
+    _say(f"  rel difference {err:.2e}")
+    assert err <= 2e-14

@@ -121,3 +121,31 @@ def test_batch_create_rejects_bad_arguments_without_touching_the_gpu():
     assert not h.value
     assert lib.sadi_batch_run(None, 1) == -5
     assert lib.sadi_batch_destroy(None) == -5
+
+
+def test_quadrature_rows_double_double_matches_extended_precision():
+    """The double-double float64 recurrence that builds the GPU's quadrature table (run here
+    on the host) against the long double one of the host set-up: every node and order k <
+    4096, relative to each value (values above 1e-250)."""
+    x, dd = P.host_quadrature_rows(4096, fp64=True)
+    _, ld = P.host_quadrature_rows(4096, fp64=False)
+    assert dd.shape == ld.shape == (x.size, 4096)
+    big = np.abs(ld) > 1e-250
+    assert np.array_equal(big, np.abs(dd) > 1e-250)
+    assert (np.abs(dd[big] - ld[big]) / np.abs(ld[big])).max() <= 2e-15
+
+
+def test_quadrature_rows_match_scipy_ive():
+    """An independent pin of the same rows: scipy.special.ive (a library routine, not ours) at
+    every node below 1e9, relative to each row's largest value; the normalisation
+    e^-x (I_0 + 2 sum_k I_k) = 1 holds where the orders cover the sum."""
+    import scipy.special as sp
+    x, dd = P.host_quadrature_rows(4096, fp64=True)
+    k = np.arange(4096)
+    sel = x < 1e9
+    ref = sp.ive(k[None, :], x[sel, None])
+    err = np.abs(dd[sel] - ref) / np.abs(ref).max(axis=1, keepdims=True)
+    assert np.nanmax(err) <= 1e-12
+    full = x < 1e4       # orders < 4096 hold the whole sum there (terms fall like e^{-k^2/2x})
+    tot = dd[full, 0] + 2 * dd[full, 1:].sum(axis=1)
+    assert np.abs(tot - 1.0).max() <= 1e-13
