@@ -124,10 +124,10 @@ sadi_status sadi_step_noalloc(sadi_ctx* ctx, double* u_prev, const double* u_cur
 
 /* nsteps >= 0 steps n >= 1.  On entry (u_prev, u_cur) = (u^{n-1}, u^n); on exit
  * (u_prev, u_cur) = (u^{n+nsteps-1}, u^{n+nsteps}).  Both arrays are work space while
- * the calls run: in float64 the steps alternate between the grid and its transpose (the
- * scheme is symmetric in x and y), with one in-place transpose before the first step and
- * one transpose or transposing exchange after the last.  The result matches nsteps calls
- * of sadi_step to rounding. */
+ * the calls run: unless the correction rank M - N exceeds 3, the steps alternate between
+ * the grid and its transpose (the scheme is symmetric in x and y), with one in-place
+ * transpose before the first step and one transpose or transposing exchange after the
+ * last, in every precision.  The result matches nsteps calls of sadi_step to rounding. */
 sadi_status sadi_run(sadi_ctx* ctx, double* u_prev, double* u_cur, int nsteps);
 
 /* In place, lines[r*ld + i] <- (H^-1 v_r)_i for r < nlines, i < N, where v_r is

@@ -804,23 +804,20 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
 // next step.  With `fwd` the same column is then transformed along its length, which is
 // the next step's row transform: its half spectrum goes to row c of S.  XS: X in paired
 // rows (single instances) or plain rows (batch members).
-// grp: this workgroup's group of ColGSCfg<M>::LPW columns; smem: ColGSCfg<M>::LDS_BYTES bytes.
-template <int M, int XS>
-__device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
-                                                 double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_,
-                                                 FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M,
-                                                 int grp, int fwd, unsigned char* smem) {
-  using Cfg = ColGSCfg<M>;
-  using L_t = typename Cfg::Line;
+// The end of a run's step for column cc of this step's grid, after its y-line solve: slot m
+// of d holds Uhat[k] in .x, k = t + T m.  u^{n+1}[k][cc] = 2 u^n[k][cc] - u^{n-1}[k][cc] + Uhat[k]
+// with ucur = u^n in this step's layout (column cc read with stride N) and prev_t = u^{n-1}
+// in the transposed layout (its row cc is column cc here, contiguous); the new column is
+// stored as row cc of prev_t.  With `fwd` it is then transformed along its length (the next
+// step's row transform): its half spectrum goes to row cc of S.
+template <class L_t>
+__device__ __forceinline__ void update_transposed_and_forward(const L_t& L, V* d, unsigned char* smem,
+                                                              const double* __restrict__ ucur,
+                                                              double* __restrict__ prev_t, int n, int cc, bool live,
+                                                              V* __restrict__ S, int lds_, const FFTTables<double>& tab,
+                                                              const V* __restrict__ root2M, int fwd) {
   constexpr int E = L_t::E, T = L_t::T;
-  const L_t L(threadIdx.x);
-  const int col = grp * Cfg::LPW + L.line;
-  const bool live = col < n;
-  const int cc = live ? col : 0;
   const int t = L.t;
-  V d[E];
-  load_column_pair<M, E, T, XS>(L, d, X, cc, ldx, smem, n);
-  gs_solve(L, d, smem, tab, gs, n);
   // an opaque copy of the lane index: the row indices below are recomputed rather than
   // kept live across the solve from the column load (register pressure)
   int tt = t;
@@ -855,6 +852,50 @@ __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, i
   }
   __syncthreads();
   real_transform_store(L, d, smem, S + pair_row(cc, lds_), live, tab, root2M);
+}
+
+// grp: this workgroup's group of ColGSCfg<M>::LPW columns; smem: ColGSCfg<M>::LDS_BYTES bytes.
+template <int M, int XS>
+__device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
+                                                 double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_,
+                                                 FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M,
+                                                 int grp, int fwd, unsigned char* smem) {
+  using Cfg = ColGSCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  const L_t L(threadIdx.x);
+  const int col = grp * Cfg::LPW + L.line;
+  const bool live = col < n;
+  const int cc = live ? col : 0;
+  V d[E];
+  load_column_pair<M, E, T, XS>(L, d, X, cc, ldx, smem, n);
+  gs_solve(L, d, smem, tab, gs, n);
+  update_transposed_and_forward(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
+}
+
+// Mixed-precision form of cols_gs_fwd: the y-line solve of column cc of X (plain rows) in
+// float32 with one float64 residual correction (or none), then the same update and next
+// row transform.
+template <int M>
+__global__ void __launch_bounds__(MixColCfg<M>::NT) SADI_OCC2
+cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
+                         double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_, FFTTables<double> tab,
+                         MixedTables mx, const V* __restrict__ root2M, int ngroups, int fwd) {
+  using Cfg = MixColCfg<M>;
+  using L_t = typename Cfg::Line;
+  constexpr int E = L_t::E, T = L_t::T;
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  const int grp = xcd_group(ngroups);
+  if (grp >= ngroups) return;   // whole workgroup
+  const L_t L(threadIdx.x);
+  const typename Cfg::Line32 Lf(threadIdx.x);
+  const int col = grp * Cfg::LPW + L.line;
+  const bool live = col < n;
+  const int cc = live ? col : 0;
+  V d[E];
+  load_column_pair<M, E, T, 0>(L, d, X, cc, ldx, smem, n);
+  mixed_solve(L, Lf, d, smem, tab, mx);
+  update_transposed_and_forward(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
 }
 
 // ----------------------------------------------------------------------------------
@@ -1516,6 +1557,16 @@ void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st) {
 }
 
 template <int M>
+void launch_cols_gs_fwd_mixed(const double* X, int ldx, const double* ucur, double* prev_t, int n, V* S, int lds_,
+                              bool fwd, const FFTTables<double>& tab, const MixedTables& mx, const V* root2M,
+                              hipStream_t st) {
+  const int ngroups = (n + MixColCfg<M>::LPW - 1) / MixColCfg<M>::LPW;
+  const int grid = ((ngroups + 7) / 8) * 8;
+  hipLaunchKernelGGL(cols_gs_fwd_mixed_kernel<M>, dim3(grid), dim3(MixColCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n,
+                     S, lds_, tab, mx, root2M, ngroups, fwd ? 1 : 0);
+}
+
+template <int M>
 void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                           int ldu, int n, const FFTTables<double>& tab, const MixedTables& mx, hipStream_t st) {
   const int ngroups = (n + MixColCfg<M>::LPW - 1) / MixColCfg<M>::LPW;
@@ -1615,6 +1666,8 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
                                         hipStream_t);                                                            \
   template void launch_cols_gs_mixed<M>(int, const double*, int, const double*, const double*, double*, int, int, \
                                         const FFTTables<double>&, const MixedTables&, hipStream_t);                \
+  template void launch_cols_gs_fwd_mixed<M>(const double*, int, const double*, double*, int, V*, int, bool,      \
+                                            const FFTTables<double>&, const MixedTables&, const V*, hipStream_t); \
   template void launch_batch_rows_fwd<M>(int, const BatchInst*, int, int, int, int, int, int,                     \
                                          const FFTTables<double>&, hipStream_t);                                  \
   template void launch_batch_cols_conv<M>(const BatchInst*, int, int, int, int, const FFTTables<double>&,         \

@@ -274,5 +274,11 @@ void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTab
 template <int M>
 void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                           int ldu, int n, const FFTTables<double>& tab, const MixedTables& mx, hipStream_t st);
+// mixed-precision y-line solves of X (plain rows), the update into prev_t's rows and, with fwd,
+// the next step's row transform (as launch_cols_gs_fwd)
+template <int M>
+void launch_cols_gs_fwd_mixed(const double* X, int ldx, const double* ucur, double* prev_t, int n, double2* S,
+                              int lds_, bool fwd, const FFTTables<double>& tab, const MixedTables& mx,
+                              const double2* root2M, hipStream_t st);
 
 }  // namespace sadi

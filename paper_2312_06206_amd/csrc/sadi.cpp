@@ -168,6 +168,12 @@ template <int M> struct ColsGSMixed {
                                   c->stream);
   }
 };
+template <int M> struct ColsGSFwdMixed {   // mixed y-sweep, update into the transposed layout, next row pass
+  static void run(const sadi_ctx* c, const double* ucur, double* prev_t, bool fwd) {
+    sadi::launch_cols_gs_fwd_mixed<M>(c->X, c->ldX, ucur, prev_t, c->n, c->S, c->ldS, fwd, tables(c), mixed_tables(c),
+                                      c->root2M, c->stream);
+  }
+};
 template <int M> struct RowsGSMixed {
   static void run(const sadi_ctx* c, double* lines, int ld, int nlines) {
     sadi::launch_rows_gs_mixed<M>(lines, ld, nlines, c->n, tables(c), mixed_tables(c), c->stream);
@@ -564,10 +570,11 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
   if (u_prev == u_cur) return fail(SADI_E_INVALID, "u_prev and u_cur must differ");
   if (nsteps < 0) return fail(SADI_E_INVALID, "nsteps must be >= 0");
   if (nsteps == 0) return SADI_OK;
-  if (c->prec == SADI_FP64 && !c->tail_gemm) {
+  if (!c->tail_gemm) {
     // Three kernels per step: the y-sweep kernel also forms u^{n+1} and the next step's row
     // transform, on the transposed grid (x and y swap roles every step).  u^{n-1} starts in
-    // the transposed layout; both arrays are back in the natural layout at the end.
+    // the transposed layout; both arrays are back in the natural layout at the end.  The
+    // float32 line solves take the same schedule (their x-sweep writes X in plain rows).
     auto mark = [&](int k) {
       hipEvent_t e = c->mark(k);
       if (e) (void)hipEventRecord(e, c->stream);
@@ -582,9 +589,15 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
       mark(1);
       dispatch_m<ColsConv>(c->m, c);
       mark(2);
-      dispatch_m<RowsRhs>(c->m, c, 0, b, nullptr, c->X, c->ldX, sc);
+      if (c->prec == SADI_FP64)
+        dispatch_m<RowsRhs>(c->m, c, 0, b, nullptr, c->X, c->ldX, sc);
+      else
+        dispatch_m<RowsRhsMixed>(c->m, c, 0, b, nullptr, sc);
       mark(3);
-      dispatch_m<ColsGSFwd>(c->m, c, b, a, s + 1 < nsteps);
+      if (c->prec == SADI_FP64)
+        dispatch_m<ColsGSFwd>(c->m, c, b, a, s + 1 < nsteps);
+      else
+        dispatch_m<ColsGSFwdMixed>(c->m, c, b, a, s + 1 < nsteps);
       mark(4);
       if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
       sadi_status st = check_launch();
@@ -598,36 +611,22 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
       sadi::launch_swap_transposed(u_cur, u_prev, c->n, c->stream);
     return check_launch();
   }
+  // corrections of rank above 3 (float64 only): four kernels per step in the natural layout,
+  // the leapfrog update of step s riding on the row transform of step s + 1
   double* a = u_prev;
   double* b = u_cur;
-  if (c->prec == SADI_FP64) {
-    // the leapfrog update of step s rides on the row transform of step s + 1
-    for (int s = 0; s < nsteps; ++s) {
-      sadi_status st = s == 0 ? enqueue_step(c, 0, b, a, nullptr, a, 2)
-                              : enqueue_step(c, 0, b, a, nullptr, a, 2, a);
-      if (st != SADI_OK) return st;
-      if (s > 0) std::swap(a, b);
-    }
-    // the pending update leaves the newest state in u_cur and the one before in u_prev
-    if (b == u_cur)
-      sadi::launch_leapfrog(2, b, a, c->X, c->ldX, nullptr, c->n, c->stream);
-    else
-      sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
-    return check_launch();
-  }
   for (int s = 0; s < nsteps; ++s) {
-    sadi_status st = enqueue_step(c, 0, b, a, nullptr, a);
+    sadi_status st = s == 0 ? enqueue_step(c, 0, b, a, nullptr, a, 2)
+                            : enqueue_step(c, 0, b, a, nullptr, a, 2, a);
     if (st != SADI_OK) return st;
-    std::swap(a, b);
+    if (s > 0) std::swap(a, b);
   }
-  if (nsteps % 2 == 1) {
-    // newest is in u_prev's buffer: exchange the two arrays through the X workspace
-    const size_t w = sizeof(double) * c->n, hgt = c->n;
-    SADI_HIP(hipMemcpy2DAsync(c->X, sizeof(double) * c->ldX, u_cur, w, w, hgt, hipMemcpyDeviceToDevice, c->stream));
-    SADI_HIP(hipMemcpyAsync(u_cur, u_prev, w * hgt, hipMemcpyDeviceToDevice, c->stream));
-    SADI_HIP(hipMemcpy2DAsync(u_prev, w, c->X, sizeof(double) * c->ldX, w, hgt, hipMemcpyDeviceToDevice, c->stream));
-  }
-  return SADI_OK;
+  // the pending update leaves the newest state in u_cur and the one before in u_prev
+  if (b == u_cur)
+    sadi::launch_leapfrog(2, b, a, c->X, c->ldX, nullptr, c->n, c->stream);
+  else
+    sadi::launch_leapfrog(0, b, a, c->X, c->ldX, a, c->n, c->stream);
+  return check_launch();
 }
 
 sadi_status sadi_toeplitz_solve(sadi_ctx* c, double* lines, int nlines, int ld) {
