@@ -305,15 +305,20 @@ __device__ __forceinline__ void toeplitz_apply64(const LineT& L, const float* x,
 
 // Mixed-precision line solve.  On entry dv[m] = (v[k], v[M-1-k]) (FP64, v[N] = 0); on exit
 // dv[m].x = x[k] with x = x0 + x1, x0 = GS32(v), x1 = GS32(v - H x0) (FP64 residual) when
-// refining, else x = x0.
+// refining, else x = x0.  keep: this line's M doubles of LDS outside the exchange region,
+// which hold v and then x0 across the solves instead of registers (each thread touches only
+// its own entries k = t + T m, so no barrier is needed around them).
 template <class Line64, class Line32>
-__device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V* dv, void* lds,
+__device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V* dv, void* lds, double* keep,
                                             const FFTTables<double>& tab, const MixedTables& mx) {
   constexpr int M = Line64::M, E = Line64::E, T = Line64::T;
   const int t = L.t;
   float2 df[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) df[m] = float2{(float)dv[m].x, (float)dv[m].y};
+  for (int m = 0; m < E; ++m) {
+    df[m] = float2{(float)dv[m].x, (float)dv[m].y};
+    if (mx.refine) (keep + T * m)[t] = dv[m].x;
+  }
   gs_solve(Lf, df, lds, mx.tab32, mx.gs32, M - 1);
   if (!mx.refine) {
 #pragma unroll
@@ -325,12 +330,14 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
 #pragma unroll
   for (int m = 0; m < E; ++m) x0[m] = df[m].x;
   if (t == T - 1) x0[E - 1] = 0.0f;   // slot k = N holds the bordering unknown, not x
-  // r = v - x0 - beta T x0  (FP64, x0 is exactly representable), r[N] = 0
+  // r = v - x0 - beta T x0  (FP64, x0 is exactly representable), r[N] = 0; x0 then takes
+  // v's place in LDS
   toeplitz_apply64(L, x0, r, lds, tab, mx.toe, mx.q64);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    r[m] = dv[m].x - (double)x0[m] - r[m];
+    r[m] = (keep + T * m)[t] - (double)x0[m] - r[m];
     if (m == E - 1 && t == T - 1) r[m] = 0.0;
+    (keep + T * m)[t] = (double)x0[m];
   }
   // reversed copy of r through LDS
   double* buf = reinterpret_cast<double*>(lds);
@@ -343,7 +350,7 @@ __device__ __forceinline__ void mixed_solve(const Line64& L, const Line32& Lf, V
   __syncthreads();
   gs_solve(Lf, df, lds, mx.tab32, mx.gs32, M - 1);
 #pragma unroll
-  for (int m = 0; m < E; ++m) dv[m].x = (double)x0[m] + (double)df[m].x;
+  for (int m = 0; m < E; ++m) dv[m].x = (keep + T * m)[t] + (double)df[m].x;
   (void)M;
 }
 
@@ -703,7 +710,7 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   using L_t = typename Cfg::Line;
   using L32 = typename Cfg::Line32;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES + Cfg::KEEP_BYTES];
   const L_t L(threadIdx.x);
   const L32 Lf(threadIdx.x);
   const int y = blockIdx.x * Cfg::LPW + L.line;
@@ -713,7 +720,7 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   V d[E];
   rhs_phase<MODE>(L, d, smem, S + pair_row(yy, lds_), u + (size_t)yy * ldu,
                   MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n);
-  mixed_solve(L, Lf, d, smem, tab, mx);
+  mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   if (live) {
 #pragma unroll
     for (int m = 0; m < E; ++m) (xo + T * m)[L.t] = d[m].x;
@@ -884,7 +891,7 @@ cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __
   using Cfg = MixColCfg<M>;
   using L_t = typename Cfg::Line;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES + Cfg::KEEP_BYTES];
   const int grp = xcd_group(ngroups);
   if (grp >= ngroups) return;   // whole workgroup
   const L_t L(threadIdx.x);
@@ -894,7 +901,7 @@ cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __
   const int cc = live ? col : 0;
   V d[E];
   load_column_pair<M, E, T, 0>(L, d, X, cc, ldx, smem, n);
-  mixed_solve(L, Lf, d, smem, tab, mx);
+  mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   update_transposed_and_forward(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
 }
 
@@ -980,7 +987,7 @@ rows_gs_mixed_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTT
   using Cfg = MixRowCfg<M>;
   using L_t = typename Cfg::Line;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES + Cfg::KEEP_BYTES];
   const L_t L(threadIdx.x);
   const typename Cfg::Line32 Lf(threadIdx.x);
   const int y = blockIdx.x * Cfg::LPW + L.line;
@@ -988,7 +995,7 @@ rows_gs_mixed_kernel(double* __restrict__ lines, int ld, int nlines, int n, FFTT
   double* row = lines + (size_t)(live ? y : 0) * ld;
   V d[E];
   load_line_pair<M, E, T>(d, row, 1, L.t, M - 1);
-  mixed_solve(L, Lf, d, smem, tab, mx);
+  mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   if (live) store_line<M, E, T>(d, row, 1, L.t, M - 1);
 }
 
@@ -999,7 +1006,7 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
   using Cfg = MixColCfg<M>;
   using L_t = typename Cfg::Line;
   constexpr int E = L_t::E, T = L_t::T;
-  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES];
+  __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES + Cfg::KEEP_BYTES];
   const int grp = xcd_group(ngroups);
   if (grp >= ngroups) return;
   const L_t L(threadIdx.x);
@@ -1009,7 +1016,7 @@ cols_gs_mixed_kernel(const double* __restrict__ X, int ldx, const double* ucur, 
   const int cc = live ? col : 0;
   V d[E];
   load_line_pair<M, E, T>(d, X + cc, ldx, L.t, M - 1);
-  mixed_solve(L, Lf, d, smem, tab, mx);
+  mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   if (live) {
     const int o = L.t * ldu + col;
     const int oe = min(L.t, T - 2) * ldu + col;

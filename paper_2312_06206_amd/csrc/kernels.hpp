@@ -114,25 +114,23 @@ template <int M> struct ColGSCfg {
 };
 
 // mixed precision (FP32 solves, optional FP64 residual correction): 2 waves per SIMD,
-// 256 threads per workgroup
-template <int M> struct MixRowCfg {
+// 256 threads per workgroup.  Beyond the exchange region (LDS_BYTES), KEEP_BYTES hold M
+// doubles per line that the solve keeps across its stages (keep(smem, line)).
+template <int M, bool FAST> struct MixCfg {
   static constexpr int T = M / Shape<M>::E;
   static constexpr int LPW = T >= 256 ? 1 : 256 / T;
-  static constexpr bool LINE_FAST = false;
+  static constexpr bool LINE_FAST = FAST;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, 2>;
   using Line32 = sadi::Line<M, float, LPW, LINE_FAST, 1>;
   static constexpr int NT = Line::NT;
   static constexpr int LDS_BYTES = Line::LDS_BYTES > Line32::LDS_BYTES ? Line::LDS_BYTES : Line32::LDS_BYTES;
+  static constexpr int KEEP_BYTES = LPW * M * (int)sizeof(double);
+  static __device__ __forceinline__ double* keep(unsigned char* smem, int line) {
+    return reinterpret_cast<double*>(smem + LDS_BYTES) + (size_t)line * M;
+  }
 };
-template <int M> struct MixColCfg {
-  static constexpr int T = M / Shape<M>::E;
-  static constexpr int LPW = T >= 256 ? 1 : 256 / T;
-  static constexpr bool LINE_FAST = true;
-  using Line = sadi::Line<M, double, LPW, LINE_FAST, 2>;
-  using Line32 = sadi::Line<M, float, LPW, LINE_FAST, 1>;
-  static constexpr int NT = Line::NT;
-  static constexpr int LDS_BYTES = Line::LDS_BYTES > Line32::LDS_BYTES ? Line::LDS_BYTES : Line32::LDS_BYTES;
-};
+template <int M> using MixRowCfg = MixCfg<M, false>;
+template <int M> using MixColCfg = MixCfg<M, true>;
 
 // everything the mixed-precision line solve needs
 struct MixedTables {
