@@ -30,6 +30,13 @@ sadi_status validate_problem(double alpha, double kappa, int n, double tau, cons
     if (e_ != hipSuccess)                                                                               \
       return sadi_impl::fail(SADI_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));         \
   } while (0)
+// the same, returning on_error(status) (a clean-up that passes the status through)
+#define SADI_HIP_OR(call, on_error)                                                                     \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      return on_error(sadi_impl::fail(SADI_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
+  } while (0)
 
 struct sadi_ctx {
   int n = 0, m = 0;

@@ -147,9 +147,10 @@ void launch_dgemm(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* b
   if (m <= 0 || n <= 0 || count <= 0) return;
   const long batches = batch ? count : 1;
   if (tile == 0) {
-    // 64 x 64 unless that leaves fewer than two blocks per CU of the 256
+    // 64 x 64 (four waves per block) unless that leaves fewer blocks than half the 256 CUs;
+    // measured on the rank-225 correction at N = 799 (169 blocks): 64 x 64 is the faster
     const long big = (long)((m + 63) / 64) * ((n + 63) / 64) * batches;
-    tile = big >= 512 ? 64 : 32;
+    tile = big >= 128 ? 64 : 32;
   }
   if (tile == 64)
     launch_shape<2, 2>(m, n, k, single, batch, count, a_rows, lda, ldb, ldc, alpha, beta, bscale, st);

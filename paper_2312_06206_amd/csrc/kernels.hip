@@ -1381,40 +1381,43 @@ rows_fwd_rect_kernel(const double* __restrict__ u, int ldu, V* __restrict__ S, i
   rows_fwd_body<M, 0, 0>(u, nullptr, nullptr, 0, ldu, S, lds_, nlen, tab, tab.root2M, nrows);
 }
 
-// G(i, k) = 2 Re S[i][k] - a_i0 for i < n, k <= M, stored transposed: GT[k][i]
+// G(i, k) = 2 Re S[i][k] - a_i0 for i < n, k <= M, stored transposed: GT[k][i]; its first
+// column also in g0[k] = G(0, k)
 __global__ void __launch_bounds__(256)
 bccb_pass1_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ a2, int n, int m,
-                  double* __restrict__ GT, int ldg) {
+                  double* __restrict__ GT, int ldg, double* __restrict__ g0) {
   const int k = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
   if (k > m) return;
-  GT[(size_t)k * ldg + i] = 2.0 * S[pair_row(i, lds_) + 2 * k].x - a2[i];
+  const double v = 2.0 * S[pair_row(i, lds_) + 2 * k].x - a2[i];
+  GT[(size_t)k * ldg + i] = v;
+  if (i == 0) g0[k] = v;
 }
 
 // Lambda(kx, ky) = (2 Re T[ky][kx] - G(0, ky)) * scale, row kx of lam: even ky at ky/2, odd
 // ky at M/2 + 1 + (ky - 1)/2
 __global__ void __launch_bounds__(256)
-bccb_pass2_kernel(const V* __restrict__ Tsp, int ldt, const double* __restrict__ GT, int ldg, int m,
-                  double* __restrict__ lam, int ldlam, double scale) {
+bccb_pass2_kernel(const V* __restrict__ Tsp, int ldt, const double* __restrict__ g0, int m, double* __restrict__ lam,
+                  int ldlam, double scale) {
   const int kx = blockIdx.x * 256 + threadIdx.x, ky = blockIdx.y;
   if (kx > m) return;
   const int pos = (ky % 2 == 0) ? ky / 2 : m / 2 + 1 + (ky - 1) / 2;
-  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[pair_row(ky, ldt) + 2 * kx].x - GT[(size_t)ky * ldg]) * scale;
+  lam[(size_t)kx * ldlam + pos] = (2.0 * Tsp[pair_row(ky, ldt) + 2 * kx].x - g0[ky]) * scale;
 }
 
 template <int M>
-void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg, V* work_spec, int ldt,
+void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg, double* g0, V* work_spec, int ldt,
                              double* lam, int ldlam, const FFTTables<double>& tab, hipStream_t st) {
   // pass 1: transforms of the rows of a2 (n rows of n) into work_spec (n rows, pitch ldt)
   hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((n + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW),
                      dim3(RowFwdCfg<M>::NT), 0, st, a2, n, work_spec, ldt, n, n, tab);
   hipLaunchKernelGGL(bccb_pass1_kernel, dim3((M + 1 + 255) / 256, n), dim3(256), 0, st, work_spec, ldt, a2, n, M,
-                     work_real, ldg);
+                     work_real, ldg, g0);
   // pass 2: transforms of the M + 1 rows of G^T (n values each)
   hipLaunchKernelGGL(rows_fwd_rect_kernel<M>, dim3((M + 1 + RowFwdCfg<M>::LPW - 1) / RowFwdCfg<M>::LPW),
                      dim3(RowFwdCfg<M>::NT), 0, st, work_real, ldg, work_spec, ldt, M + 1, n, tab);
   const double p = 2.0 * M;
-  hipLaunchKernelGGL(bccb_pass2_kernel, dim3((M + 1 + 255) / 256, M + 1), dim3(256), 0, st, work_spec, ldt, work_real,
-                     ldg, M, lam, ldlam, 1.0 / (p * p));
+  hipLaunchKernelGGL(bccb_pass2_kernel, dim3((M + 1 + 255) / 256, M + 1), dim3(256), 0, st, work_spec, ldt, g0, M,
+                     lam, ldlam, 1.0 / (p * p));
 }
 
 // ----------------------------------------------------------------------------------
@@ -1684,7 +1687,7 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
   template void launch_batch_cols_gs<M>(const BatchInst*, int, int, int, const FFTTables<double>&, hipStream_t); \
   template void launch_batch_cols_gs_fwd<M>(const BatchInst*, int, int, int, int, int, int,                      \
                                             const FFTTables<double>&, hipStream_t);                              \
-  template void launch_bccb_eigenvalues<M>(const double*, int, double*, int, V*, int, double*, int,              \
+  template void launch_bccb_eigenvalues<M>(const double*, int, double*, int, double*, V*, int, double*, int,     \
                                            const FFTTables<double>&, hipStream_t);
 
 SADI_FOR_EACH_M(SADI_INSTANTIATE)

@@ -247,11 +247,12 @@ void launch_batch_swap_transposed(const BatchInst* bi, int count, int n, hipStre
 
 // set-up: eigenvalues of the block-circulant embedding of the N x N coefficients a2 (device,
 // row-major, pitch N) into lam ((M+1) rows, pitch ldlam, even ky then odd ky per row kx,
-// scaled 1/P^2).  work_real: (M+1) x ldg doubles (ldg >= N); work_spec: (M+1) x ldt complex
-// (ldt >= M+1).
+// scaled 1/P^2).  work_real: (M+1) x ldg doubles (ldg >= N; may be lam itself); g0: M+1
+// doubles; work_spec: M+2 rows of ldt complex (ldt >= M+1), rows in pairs.  None of them may
+// overlap a2 except as stated.
 template <int M>
-void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg, double2* work_spec, int ldt,
-                             double* lam, int ldlam, const FFTTables<double>& tab, hipStream_t st);
+void launch_bccb_eigenvalues(const double* a2, int n, double* work_real, int ldg, double* g0, double2* work_spec,
+                             int ldt, double* lam, int ldlam, const FFTTables<double>& tab, hipStream_t st);
 
 // adjoint of a step (per-row partial sums in partial[4 j + k], then one finishing block)
 void launch_adjoint_dots(int mode, const double* a, const double* p, const double* q, int ldx, const double* uprev,

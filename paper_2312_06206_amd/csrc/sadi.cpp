@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -136,9 +137,10 @@ template <int M> struct RowsFwdPitched {  // spectrum of a grid function with ro
     sadi::launch_rows_fwd<M>(u, nullptr, nullptr, c->ldX, ld, c->S, c->ldS, c->n, tables(c), c->root2M, c->stream);
   }
 };
-template <int M> struct BccbEig {
-  static void run(const sadi_ctx* c, const double* a2d, double* gt, double2* spec) {
-    sadi::launch_bccb_eigenvalues<M>(a2d, c->n, gt, c->n, spec, c->ldS, c->lam2d, c->ldlam, tables(c), c->stream);
+template <int M> struct BccbEig {   // work_real may be lam2d itself (see launch_bccb_eigenvalues)
+  static void run(const sadi_ctx* c, const double* a2d, double* work_real, double* g0, double2* spec) {
+    sadi::launch_bccb_eigenvalues<M>(a2d, c->n, work_real, c->ldlam, g0, spec, c->ldS, c->lam2d, c->ldlam, tables(c),
+                                     c->stream);
   }
 };
 template <int M> struct RowsGS {
@@ -330,123 +332,118 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     }
   }
 
-  // ---- device allocations
+  // ---- device memory: one allocation.  The tables (and the set-up's temporary factors at
+  // the start of S) are filled from one host staging buffer with one copy; during set-up X
+  // holds a_ij, S the row transforms and lam2d the intermediate of the eigenvalue passes.
   c->ldS = m + 8;           // complex elements per row of the half spectrum (>= M+1); rows in pairs
   c->ldX = m;
-  sadi_status st;
-  if ((st = c->alloc((void**)&c->rootM, sizeof(double2) * sh.T)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->rootS, sizeof(double2) * sh.E)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->root2M, sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->lam_s, sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->lam_c, sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->f, sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->lam2d, sizeof(double) * lam_elems)) != SADI_OK) return bail(st);
-  // rows stored in interleaved pairs: ceil(N / 2) pairs of 2 ldS complex values
-  if ((st = c->alloc((void**)&c->S, sizeof(double2) * (size_t)(n + 1) * c->ldS)) != SADI_OK) return bail(st);
   // X: N rows (paired rows: ceil(N / 2) pairs of 2 ldX values), or the M rows of the bordered
   // y-line solutions when the correction is a GEMM
   const size_t xrows = c->tail_gemm ? (size_t)m : (size_t)n + 1;
-  if ((st = c->alloc((void**)&c->X, sizeof(double) * xrows * c->ldX)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->rootM32, sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->rootS32, sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->q32, sizeof(float2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->lam_s32, sizeof(float2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->lam_c32, sizeof(float2) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->f32, sizeof(float) * n)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->sig_e, sizeof(double) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->sig_o, sizeof(double) * m)) != SADI_OK) return bail(st);
-  if ((st = c->alloc((void**)&c->partial, sizeof(double) * 4 * (size_t)n)) != SADI_OK) return bail(st);
-
-  auto up = [&](void* dst, const void* src, size_t bytes) -> sadi_status {
-    hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return fail(SADI_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
-    return SADI_OK;
+  // S: N rows stored in interleaved pairs; M + 2 rows during set-up (the eigenvalue passes)
+  const size_t srows = std::max((size_t)n + 1, (size_t)m + 2);
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
   };
-  if ((st = up(c->rootM, hrootM.data(), sizeof(double2) * sh.T)) != SADI_OK) return bail(st);
-  if ((st = up(c->rootS, hrootS.data(), sizeof(double2) * sh.E)) != SADI_OK) return bail(st);
-  if ((st = up(c->root2M, hroot2M.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->lam_s, hls.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->lam_c, hlc.data(), sizeof(double2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->f, gsd.f.data(), sizeof(double) * gsd.f.size())) != SADI_OK) return bail(st);
-  if ((st = up(c->rootM32, hrootM32.data(), sizeof(float2) * sh.T)) != SADI_OK) return bail(st);
-  if ((st = up(c->rootS32, hrootS32.data(), sizeof(float2) * sh.E)) != SADI_OK) return bail(st);
-  if ((st = up(c->q32, hq32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->lam_s32, hls32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->lam_c32, hlc32.data(), sizeof(float2) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->f32, hf32.data(), sizeof(float) * n)) != SADI_OK) return bail(st);
-  if ((st = up(c->sig_e, hsig_e.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
-  if ((st = up(c->sig_o, hsig_o.data(), sizeof(double) * m)) != SADI_OK) return bail(st);
-
-  // ---- a_ij on the device unless a table was given: the quadrature over the nodes and the
-  // high tail as two matrix-core products, then the exact corner; then the eigenvalues of
-  // the block-circulant embedding of L_h with the row transform: two passes of
-  // even-extension DFTs (temporaries freed)
+  const size_t o_rootM = place(sizeof(double2) * sh.T), o_rootS = place(sizeof(double2) * sh.E),
+               o_root2M = place(sizeof(double2) * m), o_ls = place(sizeof(double2) * m),
+               o_lc = place(sizeof(double2) * m), o_f = place(sizeof(double) * gsd.f.size()),
+               o_rootM32 = place(sizeof(float2) * sh.T), o_rootS32 = place(sizeof(float2) * sh.E),
+               o_q32 = place(sizeof(float2) * m), o_ls32 = place(sizeof(float2) * m),
+               o_lc32 = place(sizeof(float2) * m), o_f32 = place(sizeof(float) * n),
+               o_sige = place(sizeof(double) * m), o_sigo = place(sizeof(double) * m),
+               o_partial = place(sizeof(double) * 4 * (size_t)n);
+  // the set-up's factors of a_ij at the start of S: node weights, high-tail rows (for small N
+  // they take more room than the spectrum)
+  const size_t ft = ls ? (size_t)ls->ht * n : 0;
+  const size_t fbytes = ls ? sizeof(double) * (ls->nq + 2 * ft) : 0;
+  const size_t o_S = place(std::max(sizeof(double2) * srows * c->ldS, fbytes));
+  const size_t o_X = place(sizeof(double) * xrows * c->ldX);
+  const size_t o_lam = place(sizeof(double) * lam_elems);
+  const size_t o_fw = o_S, o_fa = o_fw + sizeof(double) * (ls ? ls->nq : 0), o_fc = o_fa + sizeof(double) * ft;
+  const size_t staged = o_S + fbytes;
+  sadi_status st;
+  unsigned char* pool = nullptr;
+  if ((st = c->alloc((void**)&pool, off)) != SADI_OK) return bail(st);
+  c->rootM = (double2*)(pool + o_rootM);
+  c->rootS = (double2*)(pool + o_rootS);
+  c->root2M = (double2*)(pool + o_root2M);
+  c->lam_s = (double2*)(pool + o_ls);
+  c->lam_c = (double2*)(pool + o_lc);
+  c->f = (double*)(pool + o_f);
+  c->rootM32 = (float2*)(pool + o_rootM32);
+  c->rootS32 = (float2*)(pool + o_rootS32);
+  c->q32 = (float2*)(pool + o_q32);
+  c->lam_s32 = (float2*)(pool + o_ls32);
+  c->lam_c32 = (float2*)(pool + o_lc32);
+  c->f32 = (float*)(pool + o_f32);
+  c->sig_e = (double*)(pool + o_sige);
+  c->sig_o = (double*)(pool + o_sigo);
+  c->partial = (double*)(pool + o_partial);
+  c->S = (double2*)(pool + o_S);
+  c->X = (double*)(pool + o_X);
+  c->lam2d = (double*)(pool + o_lam);
   {
-    double* a2d = nullptr;
-    double* gt = nullptr;
-    double2* spec = nullptr;
-    double* fw = nullptr;
-    double* fa = nullptr;
-    double* fc = nullptr;
-    auto tmp = [&](void** p, size_t bytes) -> sadi_status {
-      hipError_t e = hipMalloc(p, bytes);
-      if (e != hipSuccess) {
-        *p = nullptr;
-        return fail(SADI_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
-      }
-      return SADI_OK;
+    std::vector<unsigned char> host(staged, 0);
+    auto put = [&](size_t o, const void* src, size_t bytes) {
+      if (bytes) std::memcpy(host.data() + o, src, bytes);
     };
-    auto drop = [&]() {
-      for (void* p : {(void*)a2d, (void*)gt, (void*)spec, (void*)fw, (void*)fa, (void*)fc})
-        if (p) (void)hipFree(p);
-    };
-    const size_t nn = (size_t)n * n;
-    if ((st = tmp((void**)&a2d, sizeof(double) * nn)) != SADI_OK ||
-        (st = tmp((void**)&gt, sizeof(double) * (size_t)(m + 1) * n)) != SADI_OK ||
-        (st = tmp((void**)&spec, sizeof(double2) * (size_t)(m + 2) * c->ldS)) != SADI_OK) {
-      drop();
-      return bail(st);
+    put(o_rootM, hrootM.data(), sizeof(double2) * sh.T);
+    put(o_rootS, hrootS.data(), sizeof(double2) * sh.E);
+    put(o_root2M, hroot2M.data(), sizeof(double2) * m);
+    put(o_ls, hls.data(), sizeof(double2) * m);
+    put(o_lc, hlc.data(), sizeof(double2) * m);
+    put(o_f, gsd.f.data(), sizeof(double) * gsd.f.size());
+    put(o_rootM32, hrootM32.data(), sizeof(float2) * sh.T);
+    put(o_rootS32, hrootS32.data(), sizeof(float2) * sh.E);
+    put(o_q32, hq32.data(), sizeof(float2) * m);
+    put(o_ls32, hls32.data(), sizeof(float2) * m);
+    put(o_lc32, hlc32.data(), sizeof(float2) * m);
+    put(o_f32, hf32.data(), sizeof(float) * n);
+    put(o_sige, hsig_e.data(), sizeof(double) * m);
+    put(o_sigo, hsig_o.data(), sizeof(double) * m);
+    if (ls) {
+      put(o_fw, ls->w.data(), sizeof(double) * ls->nq);
+      put(o_fa, ls->tail_a.data(), sizeof(double) * ft);
+      put(o_fc, ls->tail_c.data(), sizeof(double) * ft);
     }
+    SADI_HIP_OR(hipMemcpy(pool, host.data(), staged, hipMemcpyHostToDevice), bail);
+  }
+
+  // ---- a_ij into X, on the device unless a table was given: the quadrature over the nodes
+  // and the high tail as two matrix-core products, then the exact corner.  Then the
+  // eigenvalues of the block-circulant embedding of L_h with the row transform: two passes
+  // of even-extension DFTs through S, the intermediate in lam2d (its first column also after
+  // a_ij in X).
+  {
+    double* a2d = c->X;
+    const size_t nn = (size_t)n * n;
     if (ls) {
       const double* rows = nullptr;
       const double* low = nullptr;
       int ldr = 0;
-      if ((st = sadi::quadrature_table(&rows, &ldr, &low)) != SADI_OK) {
-        drop();
-        return bail(st);
-      }
-      const size_t ft = (size_t)ls->ht * n;
-      if ((st = tmp((void**)&fw, sizeof(double) * ls->nq)) != SADI_OK ||
-          (st = tmp((void**)&fa, sizeof(double) * ft)) != SADI_OK ||
-          (st = tmp((void**)&fc, sizeof(double) * ft)) != SADI_OK ||
-          (st = up(fw, ls->w.data(), sizeof(double) * ls->nq)) != SADI_OK ||
-          (st = up(fa, ls->tail_a.data(), sizeof(double) * ft)) != SADI_OK ||
-          (st = up(fc, ls->tail_c.data(), sizeof(double) * ft)) != SADI_OK) {
-        drop();
-        return bail(st);
-      }
+      if ((st = sadi::quadrature_table(&rows, &ldr, &low)) != SADI_OK) return bail(st);
+      const double* fw = (const double*)(pool + o_fw);
+      const double* fa = (const double*)(pool + o_fa);
+      const double* fc = (const double*)(pool + o_fc);
       // a2d[j n + i] = scale (sum_q R[q][j] w_q R[q][i] + sum_p C_p(j) A_p(i)), R the node rows
       sadi::launch_dgemm(n, n, ls->nq, sadi::GemmPtrs{rows, rows, a2d}, nullptr, 1, false, ldr, ldr, n, ls->scale,
                          0.0, c->stream, 0, fw);
       sadi::launch_dgemm(n, n, ls->ht, sadi::GemmPtrs{fc, fa, a2d}, nullptr, 1, false, n, n, n, ls->scale, 1.0,
                          c->stream);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess)
-        e = hipMemcpy2DAsync(a2d, sizeof(double) * n, ls->corner.data(), sizeof(double) * ls->nc,
-                             sizeof(double) * ls->nc, ls->nc, hipMemcpyHostToDevice, c->stream);
-      if (e != hipSuccess) {
-        drop();
-        return bail(fail(SADI_E_DEVICE, std::string("coefficient product: ") + hipGetErrorString(e)));
-      }
-    } else if ((st = up(a2d, a2.data(), sizeof(double) * nn)) != SADI_OK) {
-      drop();
-      return bail(st);
+      SADI_HIP_OR(hipGetLastError(), bail);
+      SADI_HIP_OR(hipMemcpy2DAsync(a2d, sizeof(double) * n, ls->corner.data(), sizeof(double) * ls->nc,
+                                   sizeof(double) * ls->nc, ls->nc, hipMemcpyHostToDevice, c->stream),
+                  bail);
+    } else {
+      SADI_HIP_OR(hipMemcpy(a2d, a2.data(), sizeof(double) * nn, hipMemcpyHostToDevice), bail);
     }
-    dispatch_m<BccbEig>(m, c, a2d, gt, spec);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    drop();
-    if (e != hipSuccess) return bail(fail(SADI_E_DEVICE, std::string("eigenvalue set-up: ") + hipGetErrorString(e)));
+    dispatch_m<BccbEig>(m, c, a2d, c->lam2d, a2d + nn, c->S);
+    SADI_HIP_OR(hipGetLastError(), bail);
+    SADI_HIP_OR(hipStreamSynchronize(c->stream), bail);
   }
   // the static work space of sadi_step_noalloc on this device
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SADI_E_DEVICE, "hipGetDevice"));
