@@ -153,6 +153,14 @@ sadi_status sadi_apply_lh(sadi_ctx* ctx, const double* u, double* out);
 sadi_status sadi_set_kernel_timing(sadi_ctx* ctx, int enable);
 sadi_status sadi_get_kernel_times(sadi_ctx* ctx, double* ms, long long* count);
 
+/* The context's Gohberg-Semencul tables (Proposition 1, Algorithm 1) copied to host memory:
+ * lam_s, lam_c (M complex values each, as 2M doubles re/im) and the correction f ((M - N) x N
+ * values; f[k] = c[M-1-k] / c[0] when N + 1 = M).  Any pointer may be NULL.  When N + 1 = M
+ * they were formed on the device (double-double Levinson-Durbin recursion for
+ * c = H_M^-1 e_1, then direct DFTs); sadi_host_line_tables gives the host's own.
+ * Host-synchronous. */
+sadi_status sadi_get_line_tables(const sadi_ctx* ctx, double* lam_s, double* lam_c, double* f);
+
 /* Sizes of the context: N, M = N+1, and device bytes held (any pointer may be NULL). */
 sadi_status sadi_get_info(const sadi_ctx* ctx, int* n, int* m, long long* device_bytes);
 
@@ -179,6 +187,12 @@ sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out);
  * extended precision); out has n+1 entries. */
 sadi_status sadi_host_line_generator(double alpha, double kappa, int n, double tau, const double* domain,
                                      double* out);
+
+/* The same tables computed on the host (extended-precision Levinson-Durbin recursion and
+ * FFTs), for the problem sadi_setup would build: lam_s, lam_c: 2M doubles each; f: (M - N) N
+ * doubles.  Host pointers. */
+sadi_status sadi_host_line_tables(double alpha, double kappa, int n, double tau, const double* domain,
+                                  double* lam_s, double* lam_c, double* f);
 
 /* Node rows of the quadrature that gives a_ij (the subordination integral above, on
  * nodes t_q equally spaced in log t): *nodes receives their number, x (if not NULL) the

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     Solver,
     host_laplacian_coeffs,
     host_line_generator,
+    host_line_tables,
     host_quadrature_rows,
     host_riesz_coeffs,
     load_library,

@@ -62,6 +62,8 @@ def load_library() -> ctypes.CDLL:
         "sadi_host_laplacian_coeffs": (I, [D, I, DP]),
         "sadi_host_line_generator": (I, [D, D, I, D, DP, DP]),
         "sadi_host_quadrature_rows": (I, [I, I, P(I), DP, DP]),
+        "sadi_host_line_tables": (I, [D, D, I, D, DP, DP, DP, DP]),
+        "sadi_get_line_tables": (I, [VP, DP, DP, DP]),
         "sadi_adjoint_step": (I, [VP, I, VP, VP, VP, VP, VP, VP, VP]),
         "sadi_batch_create": (I, [I, P(I), DP, DP, D, DP, I, P(VP)]),
         "sadi_batch_bind": (I, [VP, P(VP), P(VP), P(VP)]),
@@ -129,6 +131,23 @@ def host_quadrature_rows(nrows: int, fp64: bool = False):
     return x, rows
 
 
+def _line_size(n: int) -> int:
+    m = 16
+    while m < n + 1:
+        m *= 2
+    return m
+
+
+def host_line_tables(alpha, kappa, n, tau, domain=(-1.0, 1.0)):
+    """(lam_s, lam_c, f) of the line matrix from the host's extended-precision set-up:
+    complex arrays of M values and f of (M - N) x N."""
+    m = _line_size(n)
+    ls, lc, f = np.empty(2 * m), np.empty(2 * m), np.empty((m - n) * n)
+    dom = np.asarray(domain, dtype=np.float64)
+    _check(load_library().sadi_host_line_tables(alpha, kappa, n, tau, _dptr(dom), _dptr(ls), _dptr(lc), _dptr(f)))
+    return ls.view(np.complex128), lc.view(np.complex128), f.reshape(m - n, n)
+
+
 # ---- device solver ---------------------------------------------------------------
 def _grid_ptr(t, n: int) -> int:
     import torch
@@ -178,6 +197,13 @@ class Solver:
         return {"n": n.value, "m": m.value, "device_bytes": b.value}
 
     KERNELS = ("rows_fwd", "cols_conv", "rows_rhs_gs", "cols_gs")
+
+    def line_tables(self):
+        """(lam_s, lam_c, f) as the context holds them (see host_line_tables)."""
+        m = self.info["m"]
+        ls, lc, f = np.empty(2 * m), np.empty(2 * m), np.empty((m - self.n) * self.n)
+        _check(load_library().sadi_get_line_tables(self._ctx, _dptr(ls), _dptr(lc), _dptr(f)))
+        return ls.view(np.complex128), lc.view(np.complex128), f.reshape(m - self.n, self.n)
 
     def set_kernel_timing(self, enable: bool = True):
         _check(load_library().sadi_set_kernel_timing(self._ctx, int(bool(enable))))

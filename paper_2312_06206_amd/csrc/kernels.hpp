@@ -192,6 +192,13 @@ void launch_dgemm(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* b
                   long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st, int tile = 0,
                   const double* bscale = nullptr);
 
+// Gohberg-Semencul data of H_M (M = m <= 4096, N = M - 1) on the device: c = H_M^-1 e_1 by a
+// double-double Levinson-Durbin recursion (t = t_hi + t_lo, the first column of H_M; one
+// workgroup), then lam_s, lam_c, f (and float32 copies) as in Algorithm 1; q[j] = e^{-i pi j/M}.
+// c: m doubles of work space.
+void launch_gs_generator(const double* t_hi, const double* t_lo, int m, double* c, const double2* q, double2* lam_s,
+                         double2* lam_c, double* f, float2* lam_s32, float2* lam_c32, float* f32, hipStream_t st);
+
 // hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev),
 // hat in plain rows of pitch ldx
 template <int M>

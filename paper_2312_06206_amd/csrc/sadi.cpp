@@ -273,12 +273,31 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     return st;
   };
 
-  // ---- host tables
+  // ---- host tables.  The Gohberg-Semencul data of H_M come from the device when N + 1 = M
+  // (Levinson-Durbin in double-double, gs_tables_kernel), else from the host (gs_data, which
+  // also forms the rank-(M - N) correction); the host receives the first column of H_M in
+  // extended precision either way.
+  const bool device_gs = c->r == 1;
   sadi::GSData gsd;
-  try {
-    gsd = sadi::gs_data(a1, n, c->m, c->beta, g_setup_threads);
-  } catch (const std::exception& e) {
-    return bail(fail(SADI_E_INVALID, std::string("line matrix: ") + e.what()));
+  std::vector<double> t_hi(m), t_lo(m);
+  for (int k = 0; k < m; ++k) {
+    const long double tk = (k == 0 ? 1.0L : 0.0L) + (long double)c->beta * a1[k];
+    t_hi[k] = (double)tk;
+    t_lo[k] = (double)(tk - (long double)t_hi[k]);
+  }
+  if (device_gs) {
+    gsd.n = n;
+    gsd.m = m;
+    gsd.r = 1;
+    gsd.lam_s.assign(m, {0.0, 0.0});
+    gsd.lam_c.assign(m, {0.0, 0.0});
+    gsd.f.assign(n, 0.0);
+  } else {
+    try {
+      gsd = sadi::gs_data(a1, n, c->m, c->beta, g_setup_threads);
+    } catch (const std::exception& e) {
+      return bail(fail(SADI_E_INVALID, std::string("line matrix: ") + e.what()));
+    }
   }
   const long double pi = 3.14159265358979323846264338327950288L;
   std::vector<double2> hrootM(sh.T), hrootS(sh.E), hroot2M(m);
@@ -360,11 +379,14 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   // they take more room than the spectrum)
   const size_t ft = ls ? (size_t)ls->ht * n : 0;
   const size_t fbytes = ls ? sizeof(double) * (ls->nq + 2 * ft) : 0;
-  const size_t o_S = place(std::max(sizeof(double2) * srows * c->ldS, fbytes));
+  const size_t o_S = place(std::max(sizeof(double2) * srows * c->ldS, fbytes + sizeof(double) * 2 * m));
   const size_t o_X = place(sizeof(double) * xrows * c->ldX);
   const size_t o_lam = place(sizeof(double) * lam_elems);
   const size_t o_fw = o_S, o_fa = o_fw + sizeof(double) * (ls ? ls->nq : 0), o_fc = o_fa + sizeof(double) * ft;
-  const size_t staged = o_S + fbytes;
+  // and the first column of H_M (double-double) for the device Levinson recursion
+  const size_t tbytes = device_gs ? sizeof(double) * 2 * m : 0;
+  const size_t o_thi = o_S + fbytes, o_tlo = o_thi + sizeof(double) * m;
+  const size_t staged = o_S + fbytes + tbytes;
   sadi_status st;
   unsigned char* pool = nullptr;
   if ((st = c->alloc((void**)&pool, off)) != SADI_OK) return bail(st);
@@ -410,8 +432,24 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
       put(o_fa, ls->tail_a.data(), sizeof(double) * ft);
       put(o_fc, ls->tail_c.data(), sizeof(double) * ft);
     }
+    if (device_gs) {
+      put(o_thi, t_hi.data(), sizeof(double) * m);
+      put(o_tlo, t_lo.data(), sizeof(double) * m);
+    }
     SADI_HIP_OR(hipMemcpy(pool, host.data(), staged, hipMemcpyHostToDevice), bail);
   }
+  // set-up work runs on a stream of its own (contexts set up concurrently on several host
+  // threads overlap on the device), synchronised before returning
+  hipStream_t sst = nullptr;
+  SADI_HIP_OR(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking), bail);
+  auto bail_s = [&](sadi_status e) {
+    (void)hipStreamSynchronize(sst);
+    (void)hipStreamDestroy(sst);
+    return bail(e);
+  };
+  if (device_gs)   // c = H_M^-1 e_1 into X (free until a_ij), then the tables
+    sadi::launch_gs_generator((const double*)(pool + o_thi), (const double*)(pool + o_tlo), m, c->X, c->root2M,
+                              c->lam_s, c->lam_c, c->f, c->lam_s32, c->lam_c32, c->f32, sst);
 
   // ---- a_ij into X, on the device unless a table was given: the quadrature over the nodes
   // and the high tail as two matrix-core products, then the exact corner.  Then the
@@ -425,25 +463,29 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
       const double* rows = nullptr;
       const double* low = nullptr;
       int ldr = 0;
-      if ((st = sadi::quadrature_table(&rows, &ldr, &low)) != SADI_OK) return bail(st);
+      if ((st = sadi::quadrature_table(&rows, &ldr, &low)) != SADI_OK) return bail_s(st);
       const double* fw = (const double*)(pool + o_fw);
       const double* fa = (const double*)(pool + o_fa);
       const double* fc = (const double*)(pool + o_fc);
       // a2d[j n + i] = scale (sum_q R[q][j] w_q R[q][i] + sum_p C_p(j) A_p(i)), R the node rows
       sadi::launch_dgemm(n, n, ls->nq, sadi::GemmPtrs{rows, rows, a2d}, nullptr, 1, false, ldr, ldr, n, ls->scale,
-                         0.0, c->stream, 0, fw);
+                         0.0, sst, 0, fw);
       sadi::launch_dgemm(n, n, ls->ht, sadi::GemmPtrs{fc, fa, a2d}, nullptr, 1, false, n, n, n, ls->scale, 1.0,
-                         c->stream);
-      SADI_HIP_OR(hipGetLastError(), bail);
+                         sst);
+      SADI_HIP_OR(hipGetLastError(), bail_s);
       SADI_HIP_OR(hipMemcpy2DAsync(a2d, sizeof(double) * n, ls->corner.data(), sizeof(double) * ls->nc,
-                                   sizeof(double) * ls->nc, ls->nc, hipMemcpyHostToDevice, c->stream),
-                  bail);
+                                   sizeof(double) * ls->nc, ls->nc, hipMemcpyHostToDevice, sst),
+                  bail_s);
     } else {
-      SADI_HIP_OR(hipMemcpy(a2d, a2.data(), sizeof(double) * nn, hipMemcpyHostToDevice), bail);
+      SADI_HIP_OR(hipMemcpyAsync(a2d, a2.data(), sizeof(double) * nn, hipMemcpyHostToDevice, sst), bail_s);
     }
+    const hipStream_t own = c->stream;
+    c->stream = sst;
     dispatch_m<BccbEig>(m, c, a2d, c->lam2d, a2d + nn, c->S);
-    SADI_HIP_OR(hipGetLastError(), bail);
-    SADI_HIP_OR(hipStreamSynchronize(c->stream), bail);
+    c->stream = own;
+    SADI_HIP_OR(hipGetLastError(), bail_s);
+    SADI_HIP_OR(hipStreamSynchronize(sst), bail_s);
+    SADI_HIP_OR(hipStreamDestroy(sst), bail);
   }
   // the static work space of sadi_step_noalloc on this device
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SADI_E_DEVICE, "hipGetDevice"));
@@ -711,6 +753,15 @@ sadi_status sadi_get_kernel_times(sadi_ctx* c, double* ms, long long* count) {
   return SADI_OK;
 }
 
+sadi_status sadi_get_line_tables(const sadi_ctx* c, double* lam_s, double* lam_c, double* f) {
+  if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
+  const size_t fsize = (size_t)c->r * c->n;
+  if (lam_s) SADI_HIP(hipMemcpy(lam_s, c->lam_s, sizeof(double2) * c->m, hipMemcpyDeviceToHost));
+  if (lam_c) SADI_HIP(hipMemcpy(lam_c, c->lam_c, sizeof(double2) * c->m, hipMemcpyDeviceToHost));
+  if (f) SADI_HIP(hipMemcpy(f, c->f, sizeof(double) * fsize, hipMemcpyDeviceToHost));
+  return SADI_OK;
+}
+
 sadi_status sadi_get_info(const sadi_ctx* c, int* n, int* m, long long* bytes) {
   if (!ctx_ok(c)) return fail(SADI_E_STATE, "invalid context");
   if (n) *n = c->n;
@@ -748,6 +799,29 @@ sadi_status sadi_host_laplacian_coeffs(double alpha, int n, double* out) {
     std::memcpy(out, a.data(), sizeof(double) * a.size());
   } catch (const std::bad_alloc&) {
     return fail(SADI_E_NOMEM, "host allocation failed");
+  }
+  return SADI_OK;
+}
+
+sadi_status sadi_host_line_tables(double alpha, double kappa, int n, double tau, const double* domain,
+                                  double* lam_s, double* lam_c, double* f) {
+  if (!lam_s || !lam_c || !f) return fail(SADI_E_INVALID, "NULL output");
+  sadi_status st = validate_problem(alpha, kappa, n, tau, domain, false);
+  if (st != SADI_OK) return st;
+  try {
+    const int m = sadi::line_size(n);
+    const double h = (domain[1] - domain[0]) / (n + 1);
+    const double beta = kappa * tau * tau * std::pow(h, -alpha) / 2.0;
+    const sadi::GSData g = sadi::gs_data(sadi::riesz_coeffs(alpha, m), n, m, beta);
+    for (int k = 0; k < m; ++k) {
+      lam_s[2 * k] = g.lam_s[k].real();
+      lam_s[2 * k + 1] = g.lam_s[k].imag();
+      lam_c[2 * k] = g.lam_c[k].real();
+      lam_c[2 * k + 1] = g.lam_c[k].imag();
+    }
+    std::copy(g.f.begin(), g.f.end(), f);
+  } catch (const std::exception& e) {
+    return fail(SADI_E_INVALID, std::string("line tables: ") + e.what());
   }
   return SADI_OK;
 }

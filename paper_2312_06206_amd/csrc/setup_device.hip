@@ -29,6 +29,10 @@ constexpr int kTableRows = 4096;        // orders k < 4096 cover every N <= 4095
 // Double-double arithmetic (a value is hi + lo with |lo| <= ulp(hi)/2), enough to carry the
 // backward recurrence below through ~1e5 steps without the float64 rounding that would
 // otherwise accumulate where the recurrence neither grows nor decays (orders k << sqrt(x)).
+// The error-free sums and products below hold only if every operation is rounded on its own:
+// a product fused into the following sum (HIP's default contraction) would turn the low part
+// of a product into a double count of its rounding error, so contraction is off in this file.
+#pragma clang fp contract(off)
 struct DD {
   double hi, lo;
 };
@@ -125,7 +129,134 @@ struct DeviceTable {
 constexpr int kMaxDevices = 64;
 DeviceTable g_tables[kMaxDevices];
 
+// ---- Gohberg-Semencul data of the line matrix H_M (N + 1 = M) on the device ----------------
+
+__host__ __device__ inline DD dd_sub(DD a, DD b) { return dd_add(a, DD{-b.hi, -b.lo}); }
+// 1 / a in double-double: one Newton step on the float64 reciprocal
+__host__ __device__ inline DD dd_recip(DD a) {
+  const double q = 1.0 / a.hi;
+  const DD r = dd_sub(DD{1.0, 0.0}, dd_mul(a, DD{q, 0.0}));
+  return dd_add(DD{q, 0.0}, DD{r.hi * q, 0.0});
+}
+
+constexpr int kLevThreads = 1024;
+constexpr int kLevMaxM = 4096;
+
+// sum of v over the workgroup (red: kLevThreads / 64 + 1 entries of LDS); every thread gets the
+// total.  The caller synchronises before red is written again.
+__device__ DD block_sum_dd(DD v, DD* red) {
+  for (int off = 32; off > 0; off >>= 1) v = dd_add(v, DD{__shfl_down(v.hi, off), __shfl_down(v.lo, off)});
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    DD tot{0.0, 0.0};
+    for (int w = 0; w < kLevThreads / 64; ++w) tot = dd_add(tot, red[w]);
+    red[kLevThreads / 64] = tot;
+  }
+  __syncthreads();
+  return red[kLevThreads / 64];
+}
+
+// Levinson-Durbin recursion for T c = e_1, T the SPD Toeplitz matrix of first column t (given
+// as double-double t_hi + t_lo, m <= 4096 entries), in double-double arithmetic by one
+// workgroup: with f the solution at size k, e = sum_{i<k} t[k-i] f[i] and [f; 0] updated to
+// ([f; 0] - e [0; J f]) / (1 - e^2), pairs (i, k - i) in place.  c = f rounded to float64.
+__global__ void __launch_bounds__(kLevThreads)
+levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo, int m, double* __restrict__ c) {
+  __shared__ double fh[kLevMaxM], fl[kLevMaxM], th[kLevMaxM], tl[kLevMaxM];
+  __shared__ DD red[kLevThreads / 64 + 1];
+  for (int i = threadIdx.x; i < m; i += kLevThreads) {
+    th[i] = t_hi[i];
+    tl[i] = t_lo[i];
+    fh[i] = 0.0;
+    fl[i] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const DD f0 = dd_recip(DD{th[0], tl[0]});
+    fh[0] = f0.hi;
+    fl[0] = f0.lo;
+  }
+  __syncthreads();
+  for (int k = 1; k < m; ++k) {
+    DD acc{0.0, 0.0};
+    for (int i = threadIdx.x; i < k; i += kLevThreads)
+      acc = dd_add(acc, dd_mul(DD{th[k - i], tl[k - i]}, DD{fh[i], fl[i]}));
+    const DD e = block_sum_dd(acc, red);
+    const DD inv = dd_recip(dd_sub(DD{1.0, 0.0}, dd_mul(e, e)));
+    for (int i = threadIdx.x; 2 * i <= k; i += kLevThreads) {
+      const int j = k - i;                       // f[k] is still 0 here
+      const DD a{fh[i], fl[i]}, b{fh[j], fl[j]};
+      const DD na = dd_mul(dd_sub(a, dd_mul(e, b)), inv);
+      const DD nb = dd_mul(dd_sub(b, dd_mul(e, a)), inv);
+      fh[i] = na.hi;
+      fl[i] = na.lo;
+      if (j != i) {
+        fh[j] = nb.hi;
+        fl[j] = nb.lo;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < m; i += kLevThreads) c[i] = fh[i] + fl[i];
+}
+
+// The tables of Algorithm 1 from c = H_M^-1 e_1 (p1 = c[0]), by direct DFTs summed in
+// double-double: lam_c[k] = fft(c)[k] / M and lam_s[k] = fft(Q s)[k] / (2 p1 M) with
+// s = (p1, -c[M-1], ..., -c[1]) and Q = diag(e^{-i pi j / M}); the correction f[k] =
+// c[M-1-k] / p1 (k < N = M - 1); and their float32 copies.  q[j] = e^{-i pi j / M}, j < M.
+__global__ void __launch_bounds__(256)
+gs_tables_kernel(const double* __restrict__ c, int m, const double2* __restrict__ q, double2* __restrict__ lam_s,
+                 double2* __restrict__ lam_c, double* __restrict__ f, float2* __restrict__ lam_s32,
+                 float2* __restrict__ lam_c32, float* __restrict__ f32) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= m) return;
+  const int two_m = 2 * m;
+  // e^{-i pi idx / M} for 0 <= idx < 2M
+  auto w = [&](int idx) -> double2 {
+    const double2 v = q[idx < m ? idx : idx - m];
+    return idx < m ? v : double2{-v.x, -v.y};
+  };
+  auto mac = [](DD& re, DD& im, double x, double2 wv) {   // (re, im) += x wv
+    re = dd_add(re, dd_mul(DD{x, 0.0}, DD{wv.x, 0.0}));
+    im = dd_add(im, dd_mul(DD{x, 0.0}, DD{wv.y, 0.0}));
+  };
+  const double p1 = c[0];
+  DD cr{0.0, 0.0}, ci{0.0, 0.0}, sr{0.0, 0.0}, si{0.0, 0.0};
+  // exponent indices j 2k and j (2k + 1) modulo 2M, advanced with j
+  int ic = 0, is = 0;
+  for (int j = 0; j < m; ++j) {
+    const double cj = c[j];
+    const double sj = j == 0 ? p1 : -c[m - j];
+    mac(cr, ci, cj, w(ic));     // e^{-2 pi i j k / M}
+    mac(sr, si, sj, w(is));     // e^{-i pi j (2k + 1) / M}
+    ic += 2 * k;
+    if (ic >= two_m) ic -= two_m;
+    is += 2 * k + 1;
+    if (is >= two_m) is -= two_m;
+  }
+  const double rm = 1.0 / m, rs = 1.0 / (2.0 * p1 * m);
+  const double2 lc{(cr.hi + cr.lo) * rm, (ci.hi + ci.lo) * rm};
+  const double2 ls{(sr.hi + sr.lo) * rs, (si.hi + si.lo) * rs};
+  lam_c[k] = lc;
+  lam_s[k] = ls;
+  lam_c32[k] = float2{(float)lc.x, (float)lc.y};
+  lam_s32[k] = float2{(float)ls.x, (float)ls.y};
+  if (k < m - 1) {
+    const double fk = c[m - 1 - k] / p1;
+    f[k] = fk;
+    f32[k] = (float)fk;
+  }
+}
+
 }  // namespace
+
+void launch_gs_generator(const double* t_hi, const double* t_lo, int m, double* c, const double2* q, double2* lam_s,
+                         double2* lam_c, double* f, float2* lam_s32, float2* lam_c32, float* f32, hipStream_t st) {
+  hipLaunchKernelGGL(levinson_kernel, dim3(1), dim3(kLevThreads), 0, st, t_hi, t_lo, m, c);
+  hipLaunchKernelGGL(gs_tables_kernel, dim3((m + 255) / 256), dim3(256), 0, st, c, m, q, lam_s, lam_c, f, lam_s32,
+                     lam_c32, f32);
+}
 
 // The node table of the current device (built on first use; host-synchronous then).
 sadi_status quadrature_table(const double** rows, int* ld, const double** low) {

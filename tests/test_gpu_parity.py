@@ -567,3 +567,20 @@ def test_device_coefficients_match_host_tables(n, alpha):
     err = rel(got, ref)
     _say(f"  rel difference {err:.2e}")
     assert err <= 2e-14
+
+
+@pytest.mark.parametrize("n,alpha", [(15, 1.5), (255, 1.2), (1023, 1.8), (4095, 1.2), (4095, 1.8)])
+def test_device_line_tables_match_host(n, alpha):
+    """The Gohberg-Semencul tables a context forms on the device (double-double Levinson-Durbin
+    recursion, direct DFTs summed in double-double) against the host's extended-precision
+    set-up, element by element relative to each table's largest entry."""
+    from paper_2312_06206_amd import host_line_tables
+    _say(f"device line tables n={n} alpha={alpha}")
+    tau = 1e-3
+    ls_h, lc_h, f_h = host_line_tables(alpha, 1.0, n, tau)
+    with solver(alpha, n, tau) as s:
+        ls_d, lc_d, f_d = s.line_tables()
+    for name, d, h in (("lam_s", ls_d, ls_h), ("lam_c", lc_d, lc_h), ("f", f_d, f_h)):
+        err = np.abs(d - h).max() / np.abs(h).max()
+        _say(f"  {name}: {err:.2e}")
+        assert err <= 1e-14, name
