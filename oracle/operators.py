@@ -19,6 +19,8 @@ baseline of the benchmark may import it.
 """
 from __future__ import annotations
 
+from typing import Optional
+
 import numpy as np
 import scipy.fft
 import scipy.linalg
@@ -66,10 +68,16 @@ def lh_apply_loops(a2: np.ndarray, U: np.ndarray, h: float, alpha: float) -> np.
 
 
 class BCCBSymbol:
-    """Eigenvalues of the P x P block-circulant embedding of L_h (h^-alpha excluded)."""
+    """Eigenvalues of the P x P block-circulant embedding of L_h (h^-alpha excluded).
 
-    def __init__(self, a2: np.ndarray, n: int):
-        p = 2 * n                                       # >= 2N - 1
+    Any P >= 2N - 1 embeds the BTTB matrix exactly (section "Fast implementation based on
+    GS formula"); P = 2N unless given.  Two sizes give the same product in exact arithmetic
+    and differ only in rounding, which measures the float64 floor of L_h u."""
+
+    def __init__(self, a2: np.ndarray, n: int, p: Optional[int] = None):
+        p = 2 * n if p is None else int(p)
+        if p < 2 * n - 1:
+            raise ValueError("embedding size must be >= 2N - 1")
         e = np.zeros((p, p))
         q = a2[:n, :n]
         e[:n, :n] = q

@@ -53,6 +53,7 @@ class Problem:
     dense: Optional[bool] = None          # None: dense L_h matrix for N <= 48
     a1: Optional[np.ndarray] = None       # injected 1D coefficients (length >= N)
     a2: Optional[np.ndarray] = None       # injected 2D coefficients (N x N)
+    embed: Optional[int] = None           # size P of the BCCB embedding of L_h (None: 2N)
 
     def __post_init__(self):
         n = self.n
@@ -69,7 +70,7 @@ class Problem:
         if self.dense:
             self.L = operators.bttb_matrix(self.a2, n, self.h, self.alpha)
         else:
-            self.sym = operators.BCCBSymbol(self.a2, n)
+            self.sym = operators.BCCBSymbol(self.a2, n, self.embed)
         self._hinv = None
 
     # --- operators -------------------------------------------------------

@@ -16,6 +16,14 @@ Stored per file (plain float64 / int64 arrays, loadable with allow_pickle=False)
   meta       (n, alpha, tau, steps, seed)
 
     python tests/golden/make_long_runs.py [N alpha] ...     # default: all nine
+
+Floor runs (N<n>_a<alpha>_p<P>.npz, same contents): the same workload with the BCCB
+embedding of L_h at size P instead of 2N.  Every P >= 2N - 1 gives the same scheme in exact
+arithmetic, so the distance between the two oracle runs is the float64 rounding floor of
+the 1000-step run itself (L_h u of the smooth solution loses about eps ||L_h|| / lambda_min,
+and the leapfrog turns that into a phase error of the slow modes).
+
+    python tests/golden/make_long_runs.py --embed P N alpha
 """
 from __future__ import annotations
 
@@ -50,14 +58,14 @@ def sample_indices(n: int) -> np.ndarray:
     return np.unique(np.concatenate(rows)).astype(np.int64)
 
 
-def path_for(n: int, alpha: float) -> str:
-    return os.path.join(OUT, f"N{n}_a{alpha}.npz")
+def path_for(n: int, alpha: float, embed: int | None = None) -> str:
+    return os.path.join(OUT, f"N{n}_a{alpha}" + ("" if embed is None else f"_p{embed}") + ".npz")
 
 
-def make(n: int, alpha: float) -> None:
+def make(n: int, alpha: float, embed: int | None = None) -> None:
     wl = W.config2(n, alpha, seed=SEED, steps=STEPS)
     t0 = time.time()
-    P = S.Problem(alpha=wl.alpha, kappa=wl.kappa, n=n, tau=wl.tau)
+    P = S.Problem(alpha=wl.alpha, kappa=wl.kappa, n=n, tau=wl.tau, embed=embed)
     phi1 = wl.phi1()
     phi2 = np.zeros_like(phi1)
 
@@ -68,17 +76,21 @@ def make(n: int, alpha: float) -> None:
     prev, cur = P.run(phi1, phi2, STEPS, gemm=True, callback=progress)
     idx = sample_indices(n)
     os.makedirs(OUT, exist_ok=True)
-    tmp = path_for(n, alpha) + ".tmp.npz"
+    out = path_for(n, alpha, embed)
+    tmp = out + ".tmp.npz"
     np.savez(tmp, idx=idx, prev=prev.ravel()[idx], cur=cur.ravel()[idx],
              full_max=np.array([np.abs(prev).max(), np.abs(cur).max()]),
              full_l2=np.array([np.sqrt(np.sum(prev * prev)), np.sqrt(np.sum(cur * cur))]),
              meta=np.array([n, alpha, wl.tau, STEPS, SEED], dtype=np.float64))
-    os.replace(tmp, path_for(n, alpha))
-    print(f"N={n} alpha={alpha}: done in {time.time() - t0:.0f} s, {idx.size} samples", flush=True)
+    os.replace(tmp, out)
+    print(f"N={n} alpha={alpha} embed={embed}: done in {time.time() - t0:.0f} s, {idx.size} samples", flush=True)
 
 
 if __name__ == "__main__":
     args = sys.argv[1:]
+    embed = None
+    if args[:1] == ["--embed"]:
+        embed, args = int(args[1]), args[2:]
     jobs = [(int(args[i]), float(args[i + 1])) for i in range(0, len(args), 2)] if args else ALL
     for n, a in jobs:
-        make(n, a)
+        make(n, a, embed)

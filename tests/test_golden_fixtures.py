@@ -46,8 +46,7 @@ def _generator():
                                      (4095, 1.2), (4095, 1.5), (4095, 1.8)])
 def test_stored_long_runs(n, alpha):
     gen = _generator()
-    if not os.path.exists(gen.path_for(n, alpha)):
-        pytest.skip("stored oracle run not generated yet")
+    assert os.path.exists(gen.path_for(n, alpha)), "stored oracle run missing (tests/golden/make_long_runs.py)"
     with np.load(gen.path_for(n, alpha), allow_pickle=False) as z:
         meta, idx = z["meta"], z["idx"]
         prev, cur, fmax, fl2 = z["prev"], z["cur"], z["full_max"], z["full_l2"]

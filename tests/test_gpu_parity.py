@@ -478,8 +478,7 @@ GOLDEN_RUNS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
 def _stored_run(n, alpha):
     """The oracle's u^999, u^1000 of the 1000-step workload (tests/golden/make_long_runs.py)."""
     path = os.path.join(GOLDEN_RUNS, f"N{n}_a{alpha}.npz")
-    if not os.path.exists(path):
-        pytest.skip(f"stored oracle run {os.path.basename(path)} not generated yet")
+    assert os.path.exists(path), f"stored oracle run {os.path.basename(path)} missing (tests/golden/make_long_runs.py)"
     with np.load(path, allow_pickle=False) as z:
         return {k: z[k] for k in z.files}
 
