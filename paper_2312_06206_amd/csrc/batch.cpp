@@ -447,17 +447,17 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
     if ((st = b->alloc((void**)&g.d_inst, sizeof(sadi::BatchInst) * cnt)) != SADI_OK) return bail(st);
     if ((st = b->alloc((void**)&g.d_scratch_inst, sizeof(sadi::BatchInst) * cnt)) != SADI_OK) return bail(st);
     if (g.n > dense_max_n) continue;
-    // explicit H^-1 of every member: the line solve applied to the rows of the identity
+    // explicit H^-1 of every member: the line solve applied to the rows of the identity,
+    // both on the batch's stream
     const size_t nn = (size_t)g.n * g.n;
-    std::vector<double> eye(nn, 0.0);
-    for (int j = 0; j < g.n; ++j) eye[(size_t)j * g.n + j] = 1.0;
     g.hinv.resize(cnt);
+    double* pool = nullptr;   // one allocation for the group
+    if ((st = b->alloc((void**)&pool, sizeof(double) * nn * cnt)) != SADI_OK) return bail(st);
     std::vector<sadi::GemmPtrs> p1(cnt), p2(cnt);
     for (size_t k = 0; k < cnt; ++k) {
       sadi_ctx* c = b->ctx[g.members[k]];
-      if ((st = b->alloc((void**)&g.hinv[k], sizeof(double) * nn)) != SADI_OK) return bail(st);
-      if (hipMemcpy(g.hinv[k], eye.data(), sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(SADI_E_DEVICE, "hipMemcpy"));
+      g.hinv[k] = pool + nn * k;
+      sadi::launch_identity(g.hinv[k], g.n, b->stream);
       if ((st = sadi_toeplitz_solve(c, g.hinv[k], g.n, g.n)) != SADI_OK) return bail(st);
       double* t = reinterpret_cast<double*>(c->S);   // N x ldX doubles fit in the spectrum buffer
       p1[k] = sadi::GemmPtrs{c->X, g.hinv[k], t};

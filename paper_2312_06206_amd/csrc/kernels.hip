@@ -968,6 +968,11 @@ __device__ __forceinline__ void swap_transposed_tiles(double* cur, double* prev,
 }
 
 __global__ void __launch_bounds__(256) transpose_inplace_kernel(double* A, int n) { transpose_inplace_tiles(A, n); }
+__global__ void __launch_bounds__(256) identity_kernel(double* A, int n) {
+  const size_t nn = (size_t)n * n;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (size_t)gridDim.x * 256)
+    A[i] = (i % (size_t)(n + 1)) == 0 ? 1.0 : 0.0;
+}
 __global__ void __launch_bounds__(256) swap_transposed_kernel(double* cur, double* prev, int n) {
   swap_transposed_tiles(cur, prev, n);
 }
@@ -1554,6 +1559,13 @@ void launch_cols_gs_fwd(const double* X, int ldx, const double* ucur, double* pr
   const int grid = ((ngroups + 7) / 8) * 8;
   hipLaunchKernelGGL(cols_gs_fwd_kernel<M>, dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n, S,
                      lds_, tab, gs, root2M, ngroups, fwd ? 1 : 0);
+}
+
+void launch_identity(double* A, int n, hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  const size_t blocks = (nn + 255) / 256;
+  const int grid = blocks > 4096 ? 4096 : (int)blocks;
+  if (grid > 0) hipLaunchKernelGGL(identity_kernel, dim3(grid), dim3(256), 0, st, A, n);
 }
 
 void launch_transpose_inplace(double* A, int n, hipStream_t st) {

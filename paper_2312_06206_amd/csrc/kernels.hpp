@@ -68,10 +68,11 @@ __device__ __forceinline__ double sin_fp64(double x) {
 
 // launch shapes per kernel family (measured over N = 127..4095 and the uneven batch)
 // row line kernels: one line per workgroup from T = 128 threads per line, else 128 threads
+// with the lines' lanes interleaved (the rows of a pair of S then share every request)
 template <int M> struct RowCfg {
   static constexpr int T = M / Shape<M>::E;
   static constexpr int LPW = T >= 128 ? 1 : 128 / T;
-  static constexpr bool LINE_FAST = false;
+  static constexpr bool LINE_FAST = LPW > 1;
   static constexpr int SPLIT = 2;
   using Line = sadi::Line<M, double, LPW, LINE_FAST, SPLIT>;
   static constexpr int NT = Line::NT;
@@ -225,8 +226,9 @@ template <int M>
 void launch_cols_gs_fwd(const double* X, int ldx, const double* ucur, double* prev_t, int n, double2* S, int lds_,
                         bool fwd, const FFTTables<double>& tab, const GSTables64& gs, const double2* root2M,
                         hipStream_t st);
-// N x N: A <- A^T; (cur, prev) <- (prev^T, cur)
+// N x N: A <- A^T; (cur, prev) <- (prev^T, cur); A <- I (dense row-major, pitch N)
 void launch_transpose_inplace(double* A, int n, hipStream_t st);
+void launch_identity(double* A, int n, hipStream_t st);
 void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st);
 // batched forms (instances in blockIdx.y; iu / ip select u[0] or u[1]).  Row pass modes:
 // 0 / 1 step / start-up with the x-sweep, 3 / 4 the same without it (X = B)
