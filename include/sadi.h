@@ -225,24 +225,29 @@ sadi_status sadi_adjoint_step(sadi_ctx* c, int mode, const double* u_prev, const
  * FP64), each with its own N, alpha and kappa, advanced together.  Instances with equal N
  * form a group; every phase of a step (the passes of the delta form above) is one launch
  * over all instances of a group, or one launch over several groups (see
- * sadi_batch_set_schedule).  The two line sweeps of a group take one of two
+ * sadi_batch_set_schedule).  The two line sweeps of a group take one of three
  * paths:
- *   SADI_PATH_FFT_GS  the Gohberg-Semencul line solves (Proposition 1, Algorithm 1);
- *   SADI_PATH_DENSE   X = H^-1 B H^-1 as two batched FP64 matrix products with the explicit
- *                     inverse (H is fixed for the whole run, section "Fast implementation
- *                     based on GS formula"), computed once at creation by the line solve
- *                     on the identity.
- * sadi_batch_tune times both and keeps the faster per group.  Multi-step runs can be
+ *   SADI_PATH_FFT_GS       the Gohberg-Semencul line solves (Proposition 1, Algorithm 1);
+ *   SADI_PATH_DENSE        X = H^-1 B H^-1 as two batched FP64 matrix products with the
+ *                          explicit inverse (H is fixed for the whole run, section "Fast
+ *                          implementation based on GS formula"), computed once at creation
+ *                          by the line solve on the identity;
+ *   SADI_PATH_DENSE_MIXED  the same products with FP32 operands on the FP32 matrix cores,
+ *                          then one FP64 residual R = B - H Y H (two FP64 products with H)
+ *                          and the FP32 correction Y + H^-1 R H^-1: about FP64 accuracy
+ *                          (the FP32 error squared), the state and B staying FP64.
+ * sadi_batch_tune times them and keeps the fastest per group.  Multi-step runs can be
  * replayed from a captured HIP graph.  The batch works on its own HIP stream (see
  * sadi_batch_synchronize); the caller must have finished writing the bound arrays
  * before a call and must synchronise before reading them. */
 typedef struct sadi_batch sadi_batch;
 
-typedef enum { SADI_PATH_FFT_GS = 0, SADI_PATH_DENSE = 1 } sadi_line_path;
+typedef enum { SADI_PATH_FFT_GS = 0, SADI_PATH_DENSE = 1, SADI_PATH_DENSE_MIXED = 2 } sadi_line_path;
 
 /* count instances; n, alpha, kappa: host arrays of count entries (each validated as in
  * sadi_setup); tau and domain (host, 2 doubles) are shared.  Groups with N <= dense_max_n
- * also get the explicit inverse (N*N doubles per instance) for SADI_PATH_DENSE.
+ * also get the explicit inverse (N*N doubles per instance), its FP32 copy and H itself
+ * (N*N floats and doubles) for the two dense paths.
  * Host-synchronous; allocates everything the batch needs.  All groups start on
  * SADI_PATH_FFT_GS. */
 sadi_status sadi_batch_create(int count, const int* n, const double* alpha, const double* kappa, double tau,
@@ -267,8 +272,8 @@ sadi_status sadi_batch_run(sadi_batch* b, int nsteps);
 /* enable != 0: sadi_batch_run replays two steps at a time from a captured HIP graph. */
 sadi_status sadi_batch_set_graph(sadi_batch* b, int enable);
 
-/* Force the line-sweep path of the group with this N (SADI_E_UNSUPPORTED for
- * SADI_PATH_DENSE above dense_max_n). */
+/* Force the line-sweep path of the group with this N (SADI_E_UNSUPPORTED for the dense
+ * paths above dense_max_n). */
 sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path);
 
 /* Schedule of the step's launches: 1 (default) -- the groups on SADI_PATH_FFT_GS with
@@ -283,17 +288,18 @@ sadi_status sadi_batch_set_schedule(sadi_batch* b, int schedule);
 sadi_status sadi_batch_get_schedule(const sadi_batch* b, int* schedule, double* ms_groups, double* ms_lists);
 
 /* Autotuner: for every group, time `steps` steps of each available path on zero scratch
- * state (the bound state is not touched) -- the dense path with both tile shapes of its
+ * state (the bound state is not touched) -- the dense paths with both tile shapes of their
  * products (64 x 64 and 32 x 32 blocks of the result per workgroup) -- and keep the fastest;
  * then time the whole step under both schedules with those paths and keep the faster
  * schedule.  Host-synchronous. */
 sadi_status sadi_batch_tune(sadi_batch* b, int steps);
 
 /* Group `index` (0 <= index < groups): its N, member count, current path, the tuned
- * milliseconds per step of each path (-1 if not timed) and the tile of the dense products
- * (64 or 32; 0: chosen by the number of tiles).  Any output pointer may be NULL. */
+ * milliseconds per step of each path (-1 if not timed) and the tile of the products of the
+ * current dense path (SADI_PATH_DENSE's when on the FFT path; 64 or 32, 0: chosen by the
+ * number of tiles).  Any output pointer may be NULL. */
 sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,
-                                 double* ms_dense, int* dense_tile);
+                                 double* ms_dense, double* ms_dense_mixed, int* dense_tile);
 
 /* Instance and group counts, device bytes held by the batch. */
 sadi_status sadi_batch_get_info(const sadi_batch* b, int* count, int* groups, long long* bytes);

@@ -74,7 +74,7 @@ def load_library() -> ctypes.CDLL:
         "sadi_batch_tune": (I, [VP, I]),
         "sadi_batch_set_schedule": (I, [VP, I]),
         "sadi_batch_get_schedule": (I, [VP, P(I), DP, DP]),
-        "sadi_batch_get_group": (I, [VP, I, P(I), P(I), P(I), DP, DP, P(I)]),
+        "sadi_batch_get_group": (I, [VP, I, P(I), P(I), P(I), DP, DP, DP, P(I)]),
         "sadi_batch_get_info": (I, [VP, P(I), P(I), P(ctypes.c_longlong)]),
         "sadi_batch_synchronize": (I, [VP]),
         "sadi_batch_destroy": (I, [VP]),
@@ -304,7 +304,7 @@ class Solver:
 
 
 # ---- batches ---------------------------------------------------------------------
-PATHS = {"fft_gs": 0, "dense": 1}
+PATHS = {"fft_gs": 0, "dense": 1, "dense_mixed": 2}
 SCHEDULES = {"groups": 0, "work_lists": 1}
 
 
@@ -394,11 +394,12 @@ class Batch:
         names = {v: k for k, v in PATHS.items()}
         for i in range(ng.value):
             n, mem, path, tile = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-            mf, md = ctypes.c_double(), ctypes.c_double()
+            mf, md, mm = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
             _check(lib.sadi_batch_get_group(self._h, i, ctypes.byref(n), ctypes.byref(mem), ctypes.byref(path),
-                                            ctypes.byref(mf), ctypes.byref(md), ctypes.byref(tile)))
+                                            ctypes.byref(mf), ctypes.byref(md), ctypes.byref(mm), ctypes.byref(tile)))
             out.append({"n": n.value, "members": mem.value, "path": names[path.value],
-                        "ms_fft_gs": mf.value, "ms_dense": md.value, "dense_tile": tile.value})
+                        "ms_fft_gs": mf.value, "ms_dense": md.value, "ms_dense_mixed": mm.value,
+                        "dense_tile": tile.value})
         return out
 
     def device_bytes(self) -> int:

@@ -1,9 +1,9 @@
 // Batched S-ADI: many independent problems (their own N, alpha, kappa) advanced together.
 // Instances are grouped by N; each group runs every phase of a step as one launch over all
 // of its instances (blockIdx.y), and a run of steps can be replayed from a captured HIP
-// graph.  Per group, the two line sweeps take either the Gohberg-Semencul FFT kernels or
-// two dense products with the explicit H^-1 (batched matrix-core products); a timing pass
-// picks the faster one.
+// graph.  Per group, the two line sweeps take the Gohberg-Semencul FFT kernels, two dense
+// FP64 products with the explicit H^-1 (batched matrix-core products), or the same products
+// in FP32 with one FP64 residual refinement; a timing pass picks the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +14,7 @@
 
 #include "context.hpp"
 #include "kernels.hpp"
+#include "setup_math.hpp"
 
 using namespace sadi_impl;
 
@@ -25,14 +26,26 @@ struct Group {
   sadi::BatchInst* d_inst = nullptr;          // device copy of the members' descriptors
   sadi::BatchInst* d_scratch_inst = nullptr;  // same, state in scratch buffers (timing)
   int path = SADI_PATH_FFT_GS;
-  double ms[2] = {-1.0, -1.0};                // timed ms per step for each path
-  int dense_tile = 0;                         // tile of the dense products (0: by tile count)
+  double ms[3] = {-1.0, -1.0, -1.0};          // timed ms per step for each path
+  int tile[3] = {0, 0, 0};                    // tile of the dense products (0: by tile count)
   // dense path: H^-1 per member (rows H^-1 e_k) and the pointer triples of the two
   // products per member: T = X H^-1 into the spectrum buffer S (as real), then X = H^-1 T
   std::vector<double*> hinv;
   sadi::GemmPtrs* d_prod1 = nullptr;
   sadi::GemmPtrs* d_prod2 = nullptr;
+  // FP32 dense path with one FP64 refinement (mixed_sweeps): H^-1 in FP32 and H in FP64 per
+  // member; in the member's spectrum buffer: X32 and T32 (FP32, N x N each, later W in FP64)
+  // and Y (FP64)
+  sadi::GemmPtrs32<float>* d_m1 = nullptr;    // T32 = X32 Hinv32
+  sadi::GemmPtrs32<double>* d_m2 = nullptr;   // Y = (or +=) H^-1 T32
+  sadi::GemmPtrs* d_w = nullptr;              // W = Y H
+  sadi::GemmPtrs* d_r = nullptr;              // X = X - H W
+  sadi::CvtPtrs* d_cvt = nullptr;             // X32 = (float) X
+  sadi::CopyPtrs* d_copy = nullptr;           // X = Y
+  bool mixed_ready = false;                   // the above built (setup_mixed)
 };
+
+bool dense_path(int path) { return path == SADI_PATH_DENSE || path == SADI_PATH_DENSE_MIXED; }
 
 }  // namespace
 
@@ -123,10 +136,95 @@ template <int M> struct BColsGS {
 sadi_status dense_sweeps(sadi_batch* b, const Group& g) {
   const sadi_ctx* c = b->ctx[g.members[0]];
   const int n = g.n, cnt = (int)g.members.size();
-  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod1, cnt, true, c->ldX, n, c->ldX, 1.0, 0.0, b->stream,
-                     g.dense_tile);
-  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod2, cnt, false, n, c->ldX, c->ldX, 1.0, 0.0, b->stream,
-                     g.dense_tile);
+  const int tile = g.tile[SADI_PATH_DENSE];
+  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod1, cnt, true, c->ldX, n, c->ldX, 1.0, 0.0, b->stream, tile);
+  sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_prod2, cnt, false, n, c->ldX, c->ldX, 1.0, 0.0, b->stream, tile);
+  return check_launch();
+}
+
+// The same sweeps with FP32 products and one FP64 refinement (B in X on entry, Uhat on exit):
+//   Y = H^-1 fl32(B) H^-1 in FP32 products (FP64 result),  R = B - H Y H in FP64,
+//   Uhat = Y + H^-1 fl32(R) H^-1 in FP32 products accumulated into Y.
+// The FP32 solve has relative error ~ 1e-7 cond(H); after the correction it is that squared.
+sadi_status mixed_sweeps(sadi_batch* b, const Group& g) {
+  const sadi_ctx* c = b->ctx[g.members[0]];
+  const int n = g.n, cnt = (int)g.members.size();
+  const int tile = g.tile[SADI_PATH_DENSE_MIXED];
+  const long ldx = c->ldX;
+  for (int pass = 0; pass < 2; ++pass) {
+    sadi::launch_to_fp32(g.d_cvt, cnt, n, ldx, b->stream);                                   // X32 = fl32(X)
+    sadi::launch_sgemm(n, n, n, g.d_m1, cnt, true, n, n, n, 1.0, 0.0, b->stream, tile);     // T32 = X32 Hinv
+    sadi::launch_sgemm(n, n, n, g.d_m2, cnt, false, n, n, n, 1.0, pass ? 1.0 : 0.0, b->stream, tile);  // Y (+)= Hinv T32
+    if (pass == 0) {
+      sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_w, cnt, true, n, n, n, 1.0, 0.0, b->stream, tile);    // W = Y H
+      sadi::launch_dgemm(n, n, n, sadi::GemmPtrs{}, g.d_r, cnt, true, n, n, ldx, -1.0, 1.0, b->stream, tile);  // X -= H W
+    }
+  }
+  sadi::launch_copy_fp64(g.d_copy, cnt, n, n, ldx, b->stream);                                // X = Y
+  return check_launch();
+}
+
+// Data of SADI_PATH_DENSE_MIXED for a group with explicit inverses, built on first use (the
+// tuner or sadi_batch_set_path): H^-1 rounded to FP32, H itself in FP64 (from its first
+// column, formed on the host exactly as the line tables' generating column), and the
+// pointer arrays of mixed_sweeps.
+sadi_status setup_mixed(sadi_batch* b, Group& g) {
+  if (g.mixed_ready || g.hinv.empty()) return SADI_OK;
+  const size_t cnt = g.members.size(), nn = (size_t)g.n * g.n;
+  sadi_status st;
+  float* pool32 = nullptr;
+  double* hpool = nullptr;
+  double* tcols = nullptr;
+  if ((st = b->alloc((void**)&pool32, sizeof(float) * nn * cnt)) != SADI_OK ||
+      (st = b->alloc((void**)&hpool, sizeof(double) * nn * cnt)) != SADI_OK ||
+      (st = b->alloc((void**)&tcols, sizeof(double) * (size_t)g.n * cnt)) != SADI_OK)
+    return st;
+  std::vector<double> th((size_t)g.n * cnt);
+  std::vector<sadi::GemmPtrs32<float>> m1(cnt);
+  std::vector<sadi::GemmPtrs32<double>> m2(cnt);
+  std::vector<sadi::GemmPtrs> pw(cnt), pr(cnt);
+  std::vector<sadi::CvtPtrs> cv(cnt), cv_inv(cnt);
+  std::vector<sadi::CopyPtrs> cp(cnt);
+  std::vector<sadi::ToeplitzPtrs> tp(cnt);
+  for (size_t k = 0; k < cnt; ++k) {
+    sadi_ctx* c = b->ctx[g.members[k]];
+    const std::vector<double> a1 = sadi::riesz_coeffs(c->alpha, g.n);
+    for (int q = 0; q < g.n; ++q)
+      th[k * g.n + q] = (double)((q == 0 ? 1.0L : 0.0L) + (long double)c->beta * a1[q]);
+    float* hinv32 = pool32 + nn * k;
+    double* hm = hpool + nn * k;
+    float* x32 = reinterpret_cast<float*>(c->S);
+    float* t32 = x32 + nn;
+    double* w = reinterpret_cast<double*>(c->S);   // over X32 and T32 once they are consumed
+    double* y = w + nn;
+    cv_inv[k] = sadi::CvtPtrs{g.hinv[k], hinv32};
+    tp[k] = sadi::ToeplitzPtrs{tcols + (size_t)g.n * k, hm};
+    m1[k] = sadi::GemmPtrs32<float>{x32, hinv32, t32};
+    m2[k] = sadi::GemmPtrs32<double>{hinv32, t32, y};
+    pw[k] = sadi::GemmPtrs{y, hm, w};
+    pr[k] = sadi::GemmPtrs{hm, w, c->X};
+    cv[k] = sadi::CvtPtrs{c->X, x32};
+    cp[k] = sadi::CopyPtrs{y, c->X};
+  }
+  auto upload = [&](auto** dst, const auto& v) -> sadi_status {
+    const size_t bytes = sizeof(v[0]) * v.size();
+    sadi_status s2 = b->alloc((void**)dst, bytes);
+    if (s2 != SADI_OK) return s2;
+    if (hipMemcpy(*dst, v.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return fail(SADI_E_DEVICE, "hipMemcpy");
+    return SADI_OK;
+  };
+  sadi::CvtPtrs* d_cv_inv = nullptr;
+  sadi::ToeplitzPtrs* d_tp = nullptr;
+  if ((st = upload(&g.d_m1, m1)) != SADI_OK || (st = upload(&g.d_m2, m2)) != SADI_OK ||
+      (st = upload(&g.d_w, pw)) != SADI_OK || (st = upload(&g.d_r, pr)) != SADI_OK ||
+      (st = upload(&g.d_cvt, cv)) != SADI_OK || (st = upload(&g.d_copy, cp)) != SADI_OK ||
+      (st = upload(&d_cv_inv, cv_inv)) != SADI_OK || (st = upload(&d_tp, tp)) != SADI_OK)
+    return st;
+  if (hipMemcpy(tcols, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SADI_E_DEVICE, "hipMemcpy");
+  sadi::launch_to_fp32(d_cv_inv, (int)cnt, g.n, g.n, b->stream);
+  sadi::launch_toeplitz_fill(d_tp, (int)cnt, g.n, b->stream);
+  g.mixed_ready = true;
   return check_launch();
 }
 
@@ -226,7 +324,7 @@ sadi_status batch_step(sadi_batch* b, bool scratch, bool first, int lf, int iu, 
       dispatch_m<BColsGS>(g.m, b, g, bi);
     } else {
       dispatch_m<BRowsRhs>(g.m, b, g, bi, first ? 4 : 3, su);
-      sadi_status st = dense_sweeps(b, g);
+      sadi_status st = g.path == SADI_PATH_DENSE ? dense_sweeps(b, g) : mixed_sweeps(b, g);
       if (st != SADI_OK) return st;
     }
   }
@@ -539,11 +637,15 @@ sadi_status sadi_batch_set_graph(sadi_batch* b, int enable) {
 
 sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path) {
   if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
-  if (path != SADI_PATH_FFT_GS && path != SADI_PATH_DENSE) return fail(SADI_E_INVALID, "unknown path");
+  if (path != SADI_PATH_FFT_GS && !dense_path(path)) return fail(SADI_E_INVALID, "unknown path");
   for (Group& g : b->groups) {
     if (g.n != n) continue;
-    if (path == SADI_PATH_DENSE && g.hinv.empty())
+    if (dense_path(path) && g.hinv.empty())
       return fail(SADI_E_UNSUPPORTED, "no explicit inverse for N = " + std::to_string(n) + " (above dense_max_n)");
+    if (path == SADI_PATH_DENSE_MIXED) {
+      const sadi_status st = setup_mixed(b, g);
+      if (st != SADI_OK) return st;
+    }
     g.path = path;
     b->drop_graph();
     return b->bound ? build_worklists(b) : SADI_OK;
@@ -588,7 +690,7 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
     cleanup();
     return fail(SADI_E_DEVICE, "hipEventCreate");
   }
-  for (Group& g : b->groups) g.ms[0] = g.ms[1] = -1.0;
+  for (Group& g : b->groups) g.ms[0] = g.ms[1] = g.ms[2] = -1.0;
   const std::vector<int> saved = [&] {
     std::vector<int> v;
     for (Group& g : b->groups) v.push_back(g.path);
@@ -606,14 +708,16 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
   std::vector<Group> all;
   all.swap(b->groups);
   for (size_t gi = 0; gi < all.size() && st == SADI_OK; ++gi) {
+    if ((st = setup_mixed(b, all[gi])) != SADI_OK) break;
     b->groups.assign(1, all[gi]);
-    // the Gohberg-Semencul path, then the dense path with each tile shape of its products
-    const int variants[3][2] = {{SADI_PATH_FFT_GS, 0}, {SADI_PATH_DENSE, 64}, {SADI_PATH_DENSE, 32}};
-    for (int v = 0; v < 3 && st == SADI_OK; ++v) {
+    // the Gohberg-Semencul path, then both dense paths with each tile shape of their products
+    const int variants[5][2] = {{SADI_PATH_FFT_GS, 0},      {SADI_PATH_DENSE, 64},      {SADI_PATH_DENSE, 32},
+                                {SADI_PATH_DENSE_MIXED, 64}, {SADI_PATH_DENSE_MIXED, 32}};
+    for (int v = 0; v < 5 && st == SADI_OK; ++v) {
       const int path = variants[v][0];
-      if (path == SADI_PATH_DENSE && all[gi].hinv.empty()) continue;
+      if (dense_path(path) && all[gi].hinv.empty()) continue;
       b->groups[0].path = path;
-      b->groups[0].dense_tile = variants[v][1];
+      b->groups[0].tile[path] = variants[v][1];
       st = batch_run(b, true, 2, false);   // warm-up
       if (st != SADI_OK) break;
       (void)hipEventRecord(e0, b->stream);
@@ -625,7 +729,7 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
       const double per = ms / steps;
       if (all[gi].ms[path] < 0.0 || per < all[gi].ms[path]) {
         all[gi].ms[path] = per;
-        if (path == SADI_PATH_DENSE) all[gi].dense_tile = variants[v][1];
+        all[gi].tile[path] = variants[v][1];
       }
     }
     b->groups.clear();
@@ -634,9 +738,11 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     Group& g = b->groups[gi];
     g.path = saved[gi];
-    if (st == SADI_OK)
-      g.path = (g.ms[SADI_PATH_DENSE] >= 0.0 && g.ms[SADI_PATH_DENSE] < g.ms[SADI_PATH_FFT_GS]) ? SADI_PATH_DENSE
-                                                                                                 : SADI_PATH_FFT_GS;
+    if (st == SADI_OK) {
+      g.path = SADI_PATH_FFT_GS;
+      for (int p : {SADI_PATH_DENSE, SADI_PATH_DENSE_MIXED})
+        if (g.ms[p] >= 0.0 && g.ms[p] < g.ms[g.path]) g.path = p;
+    }
   }
   // then the schedule of the whole step with those paths: every group on its own, or the
   // FFT groups up to kWorkListMaxM sharing one launch per phase
@@ -684,7 +790,7 @@ sadi_status sadi_batch_get_schedule(const sadi_batch* b, int* schedule, double* 
 }
 
 sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* members, int* path, double* ms_fft,
-                                 double* ms_dense, int* dense_tile) {
+                                 double* ms_dense, double* ms_dense_mixed, int* dense_tile) {
   if (!batch_ok(b)) return fail(SADI_E_STATE, "invalid batch");
   if (index < 0 || index >= (int)b->groups.size()) return fail(SADI_E_INVALID, "group index out of range");
   const Group& g = b->groups[index];
@@ -693,7 +799,8 @@ sadi_status sadi_batch_get_group(const sadi_batch* b, int index, int* n, int* me
   if (path) *path = g.path;
   if (ms_fft) *ms_fft = g.ms[SADI_PATH_FFT_GS];
   if (ms_dense) *ms_dense = g.ms[SADI_PATH_DENSE];
-  if (dense_tile) *dense_tile = g.dense_tile;
+  if (ms_dense_mixed) *ms_dense_mixed = g.ms[SADI_PATH_DENSE_MIXED];
+  if (dense_tile) *dense_tile = g.tile[g.path == SADI_PATH_DENSE_MIXED ? SADI_PATH_DENSE_MIXED : SADI_PATH_DENSE];
   return SADI_OK;
 }
 

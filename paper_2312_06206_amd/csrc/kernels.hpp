@@ -192,6 +192,35 @@ struct GemmPtrs {
 void launch_dgemm(int m, int n, int k, const GemmPtrs& single, const GemmPtrs* batch, int count, bool a_rows,
                   long lda, long ldb, long ldc, double alpha, double beta, hipStream_t st, int tile = 0,
                   const double* bscale = nullptr);
+// The same with FP32 operands on the FP32 matrix cores (v_mfma_f32_16x16x4_f32), FP32
+// accumulation, and C in FP32 or FP64 (alpha, beta and the update of C in FP64).  Batched only.
+template <typename TC> struct GemmPtrs32 {
+  const float* A;
+  const float* B;
+  TC* C;
+};
+void launch_sgemm(int m, int n, int k, const GemmPtrs32<float>* batch, int count, bool a_rows, long lda, long ldb,
+                  long ldc, double alpha, double beta, hipStream_t st, int tile = 0);
+void launch_sgemm(int m, int n, int k, const GemmPtrs32<double>* batch, int count, bool a_rows, long lda, long ldb,
+                  long ldc, double alpha, double beta, hipStream_t st, int tile = 0);
+// Element-wise helpers of the dense paths, over `count` n x n matrices (blockIdx.y):
+// dst = (float) src (src pitch lds, dst pitch n); dst = src (FP64, pitches lds and ldd);
+// H = the symmetric Toeplitz matrix of first column t (pitch n).
+struct CvtPtrs {
+  const double* src;
+  float* dst;
+};
+struct CopyPtrs {
+  const double* src;
+  double* dst;
+};
+struct ToeplitzPtrs {
+  const double* t;
+  double* H;
+};
+void launch_to_fp32(const CvtPtrs* batch, int count, int n, long lds, hipStream_t st);
+void launch_copy_fp64(const CopyPtrs* batch, int count, int n, long lds, long ldd, hipStream_t st);
+void launch_toeplitz_fill(const ToeplitzPtrs* batch, int count, int n, hipStream_t st);
 
 // Gohberg-Semencul data of H_M (M = m <= 4096, N = M - 1) on the device: c = H_M^-1 e_1 by a
 // double-double Levinson-Durbin recursion (t = t_hi + t_lo, the first column of H_M; one

@@ -74,17 +74,19 @@ def make_batch(path=None, graph=False, schedule="work_lists"):
     return b, ms, u0, u1
 
 
-MIXED = {15: "dense", 31: "fft_gs", 63: "dense", 127: "fft_gs"}
+MIXED = {15: "dense", 31: "fft_gs", 63: "dense_mixed", 127: "fft_gs"}
 
 
 @pytest.mark.parametrize("path,graph,schedule", [("fft_gs", False, "work_lists"), ("fft_gs", True, "work_lists"),
                                                  ("fft_gs", False, "groups"), ("fft_gs", True, "groups"),
                                                  ("dense", False, "work_lists"), ("dense", True, "groups"),
+                                                 ("dense_mixed", False, "groups"), ("dense_mixed", True, "work_lists"),
                                                  ("mixed", False, "work_lists"), ("mixed", True, "work_lists")])
 def test_batch_run_matches_oracle(path, graph, schedule):
-    """Both line-sweep paths (and a mix of them across groups), both launch schedules (the
-    FFT groups in shared work-list launches, or every group on its own), with and without
-    graph replay."""
+    """The three line-sweep paths (and a mix of them across groups), both launch schedules
+    (the FFT groups in shared work-list launches, or every group on its own), with and
+    without graph replay.  The FP32 dense path with its FP64 refinement keeps the FP64
+    bar."""
     _say(f"batch path={path} graph={graph} schedule={schedule}")
     b, ms, u0, u1 = make_batch(MIXED if path == "mixed" else path, graph, schedule)
     with b:
@@ -126,8 +128,10 @@ def test_batch_tune_keeps_state():
         assert all(torch.equal(x, y) for x, y in zip(before, after))
         assert sorted(g["n"] for g in groups) == sorted({m.n for m in ms})
         for g in groups:
-            assert g["ms_fft_gs"] > 0 and g["ms_dense"] > 0
-            assert g["path"] == ("dense" if g["ms_dense"] < g["ms_fft_gs"] else "fft_gs")
+            times = {"fft_gs": g["ms_fft_gs"], "dense": g["ms_dense"], "dense_mixed": g["ms_dense_mixed"]}
+            assert all(t > 0 for t in times.values())
+            assert g["path"] == min(times, key=lambda p: (times[p], p != "fft_gs"))
+            assert g["dense_tile"] in (32, 64)
         sched, ms_groups, ms_lists = b.schedule()
         assert ms_groups > 0 and ms_lists > 0
         assert sched == ("work_lists" if ms_lists <= ms_groups else "groups")
