@@ -118,6 +118,42 @@ def cpu_baseline(wl, sample_steps: int) -> dict:
             "single_thread_sample": f"2 further steps, 1 FFT worker and 1 BLAS thread, {dt1:.1f} s wall"}
 
 
+def stored_oracle_run(n: int, alpha: float, seed: int):
+    """The oracle's own 1000-step run of this workload, if one is stored (written by
+    tests/golden/make_long_runs.py from the oracle alone), else None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "long_runs", f"N{n}_a{alpha}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        ref = {k: z[k] for k in z.files}
+    if int(ref["meta"][4]) != seed:
+        return None
+    return ref
+
+
+def oracle_run_errors(s, wl, ref, precisions) -> dict:
+    """Each precision's u^999 and u^1000 (start-up step + 999 steps through sadi_run) against
+    the oracle's stored run: max error over the stored sample nodes relative to max |u| of
+    the oracle's whole grid."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    out = {}
+    for prec in precisions:
+        s.set_options(wl.g, 0.0, prec)
+        a = torch.from_numpy(np.ascontiguousarray(wl.phi1().T)).to(dev)
+        b = s.first_step(a, torch.zeros_like(a))
+        s.run(a, b, 999)
+        errs = []
+        for k, t in enumerate((a, b)):
+            g = t.cpu().numpy().T.ravel()
+            errs.append(float(np.abs(g[ref["idx"]] - ref["prev" if k == 0 else "cur"]).max() / ref["full_max"][k]))
+        out[prec] = max(errs)
+    s.set_options(wl.g, 0.0, "fp64")
+    return out
+
+
 def batched_leg(seed: int, count: int, steps: int, unbatched_sample: int) -> dict:
     """Uneven batch: `count` problems with N uniform over {127, 255, 511, 1023}, alpha ~
     U(1.1, 1.9), kappa ~ U(0.5, 2), seeded Gaussian phi1, phi2 = 0, tau = 1e-3; autotuned
@@ -400,7 +436,7 @@ def main():
     ktimes["cols_gs_fwd"] = ktimes.pop("cols_gs")   # slot 3 of a run: y-sweep + next row transform
 
     # precision variants on the same workload: speed, and the final state's difference from
-    # the FP64 path (which matches the FP64 oracle to ~1e-12 per step)
+    # the FP64 path; below, every precision against the oracle's stored 1000-step run
     variants = {}
     if not args.no_variants:
         ref_final = u1.clone()
@@ -420,6 +456,14 @@ def main():
                               "speedup_vs_fp64": dt / dtv, "rel_err_vs_fp64_path": err,
                               "steps": steps + args.warmup + 1}
         s.set_options(wl.g, 0.0, "fp64")
+    # every precision against the oracle's own 1000-step run of this workload
+    ref = stored_oracle_run(wl.n, wl.alpha, args.seed)
+    oracle_errs = None
+    if ref is not None:
+        oracle_errs = oracle_run_errors(s, wl, ref, ["fp64"] + list(variants))
+        for prec, e in oracle_errs.items():
+            if prec in variants:
+                variants[prec]["rel_err_vs_oracle_run_1000"] = e
 
     n = wl.n
     value = n * n * steps / dt
@@ -467,6 +511,7 @@ def main():
         "setup_warm_s": setup_warm_s,
         "finite": finite,
         "precision_variants": variants,
+        "rel_err_vs_oracle_run_1000": None if oracle_errs is None else oracle_errs["fp64"],
     }
     s.close()
     if not args.no_batched:
