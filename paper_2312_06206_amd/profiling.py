@@ -117,7 +117,7 @@ def write_kernel_stats_summary(stats_csv: str, n: int, out_md: str, command: str
              "```", command, "```", "",
              "| kernel | step role | calls | avg us | total ms | % |", "|---|---|---|---|---|---|"]
     for name, calls, avg, tot, pct in rows:
-        short = name.split("(")[0].replace("void ", "").replace("sadi::", "")
+        short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("sadi::", "")
         key = kernel_key(name, m) or ""
         if key:
             steps[key] = {"calls": calls, "avg_us": avg / 1e3}
