@@ -379,14 +379,15 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   // they take more room than the spectrum)
   const size_t ft = ls ? (size_t)ls->ht * n : 0;
   const size_t fbytes = ls ? sizeof(double) * (ls->nq + 2 * ft) : 0;
-  const size_t o_S = place(std::max(sizeof(double2) * srows * c->ldS, fbytes + sizeof(double) * 2 * m));
+  const size_t o_S = place(std::max(sizeof(double2) * srows * c->ldS, fbytes));
   const size_t o_X = place(sizeof(double) * xrows * c->ldX);
   const size_t o_lam = place(sizeof(double) * lam_elems);
   const size_t o_fw = o_S, o_fa = o_fw + sizeof(double) * (ls ? ls->nq : 0), o_fc = o_fa + sizeof(double) * ft;
-  // and the first column of H_M (double-double) for the device Levinson recursion
-  const size_t tbytes = device_gs ? sizeof(double) * 2 * m : 0;
-  const size_t o_thi = o_S + fbytes, o_tlo = o_thi + sizeof(double) * m;
-  const size_t staged = o_S + fbytes + tbytes;
+  // the first column of H_M (double-double) for the device Levinson recursion and its
+  // result c, in the adjoint's partial-sum space (4 N doubles, unused until a step), which
+  // nothing else of the set-up touches: the recursion runs beside the a_ij products
+  const size_t o_thi = o_partial, o_tlo = o_thi + sizeof(double) * m, o_cvec = o_tlo + sizeof(double) * m;
+  const size_t staged = o_S + fbytes;
   sadi_status st;
   unsigned char* pool = nullptr;
   if ((st = c->alloc((void**)&pool, off)) != SADI_OK) return bail(st);
@@ -440,16 +441,22 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   }
   // set-up work runs on a stream of its own (contexts set up concurrently on several host
   // threads overlap on the device), synchronised before returning
-  hipStream_t sst = nullptr;
+  hipStream_t sst = nullptr, sgs = nullptr;
   SADI_HIP_OR(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking), bail);
   auto bail_s = [&](sadi_status e) {
-    (void)hipStreamSynchronize(sst);
-    (void)hipStreamDestroy(sst);
+    for (hipStream_t q : {sst, sgs})
+      if (q) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+      }
     return bail(e);
   };
-  if (device_gs)   // c = H_M^-1 e_1 into X (free until a_ij), then the tables
-    sadi::launch_gs_generator((const double*)(pool + o_thi), (const double*)(pool + o_tlo), m, c->X, c->root2M,
-                              c->lam_s, c->lam_c, c->f, c->lam_s32, c->lam_c32, c->f32, sst);
+  if (device_gs) {   // c = H_M^-1 e_1 (one workgroup, sequential in k), then the tables
+    SADI_HIP_OR(hipStreamCreateWithFlags(&sgs, hipStreamNonBlocking), bail_s);
+    sadi::launch_gs_generator((const double*)(pool + o_thi), (const double*)(pool + o_tlo), m,
+                              (double*)(pool + o_cvec), c->root2M, c->lam_s, c->lam_c, c->f, c->lam_s32, c->lam_c32,
+                              c->f32, sgs);
+  }
 
   // ---- a_ij into X, on the device unless a table was given: the quadrature over the nodes
   // and the high tail as two matrix-core products, then the exact corner.  Then the
@@ -485,7 +492,9 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     c->stream = own;
     SADI_HIP_OR(hipGetLastError(), bail_s);
     SADI_HIP_OR(hipStreamSynchronize(sst), bail_s);
+    if (sgs) SADI_HIP_OR(hipStreamSynchronize(sgs), bail_s);
     SADI_HIP_OR(hipStreamDestroy(sst), bail);
+    if (sgs) SADI_HIP_OR(hipStreamDestroy(sgs), bail);
   }
   // the static work space of sadi_step_noalloc on this device
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SADI_E_DEVICE, "hipGetDevice"));

@@ -142,19 +142,17 @@ __host__ __device__ inline DD dd_recip(DD a) {
 constexpr int kLevThreads = 1024;
 constexpr int kLevMaxM = 4096;
 
-// sum of v over the workgroup (red: kLevThreads / 64 + 1 entries of LDS); every thread gets the
-// total.  The caller synchronises before red is written again.
+// sum of v over the workgroup (red: kLevThreads / 64 entries of LDS); every thread adds the
+// waves' partial sums itself, in the same order, so all get the same total after one
+// barrier.  The caller synchronises before red is written again.
 __device__ DD block_sum_dd(DD v, DD* red) {
   for (int off = 32; off > 0; off >>= 1) v = dd_add(v, DD{__shfl_down(v.hi, off), __shfl_down(v.lo, off)});
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    DD tot{0.0, 0.0};
-    for (int w = 0; w < kLevThreads / 64; ++w) tot = dd_add(tot, red[w]);
-    red[kLevThreads / 64] = tot;
-  }
-  __syncthreads();
-  return red[kLevThreads / 64];
+  DD tot = red[0];
+#pragma unroll
+  for (int w = 1; w < kLevThreads / 64; ++w) tot = dd_add(tot, red[w]);
+  return tot;
 }
 
 // Levinson-Durbin recursion for T c = e_1, T the SPD Toeplitz matrix of first column t (given
@@ -164,7 +162,7 @@ __device__ DD block_sum_dd(DD v, DD* red) {
 __global__ void __launch_bounds__(kLevThreads)
 levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo, int m, double* __restrict__ c) {
   __shared__ double fh[kLevMaxM], fl[kLevMaxM], th[kLevMaxM], tl[kLevMaxM];
-  __shared__ DD red[kLevThreads / 64 + 1];
+  __shared__ DD red[kLevThreads / 64];
   for (int i = threadIdx.x; i < m; i += kLevThreads) {
     th[i] = t_hi[i];
     tl[i] = t_lo[i];

@@ -4,7 +4,8 @@
   printed errors it is computed from, up to the rounding of the printed digits, so a
   transcription slip in either shows here.
 * The oracle's stored 1000-step runs (tests/golden/make_long_runs.py): one file per
-  configured grid and order, with the sample nodes the generator defines and finite values.
+  configured grid and order, with the sample nodes the generator defines and finite values;
+  and the second runs at another embedding size, close to the first but not identical.
 """
 import importlib.util
 import math
@@ -42,12 +43,15 @@ def _generator():
     return mod
 
 
-@pytest.mark.parametrize("n,alpha", [(1023, 1.2), (1023, 1.5), (1023, 1.8), (2047, 1.2), (2047, 1.5), (2047, 1.8),
-                                     (4095, 1.2), (4095, 1.5), (4095, 1.8)])
-def test_stored_long_runs(n, alpha):
+@pytest.mark.parametrize("n,alpha,embed", [(1023, 1.2, None), (1023, 1.5, None), (1023, 1.8, None),
+                                           (2047, 1.2, None), (2047, 1.5, None), (2047, 1.8, None),
+                                           (4095, 1.2, None), (4095, 1.5, None), (4095, 1.8, None),
+                                           (2047, 1.8, 4096), (4095, 1.8, 8192)])
+def test_stored_long_runs(n, alpha, embed):
     gen = _generator()
-    assert os.path.exists(gen.path_for(n, alpha)), "stored oracle run missing (tests/golden/make_long_runs.py)"
-    with np.load(gen.path_for(n, alpha), allow_pickle=False) as z:
+    path = gen.path_for(n, alpha, embed)
+    assert os.path.exists(path), "stored oracle run missing (tests/golden/make_long_runs.py)"
+    with np.load(path, allow_pickle=False) as z:
         meta, idx = z["meta"], z["idx"]
         prev, cur, fmax, fl2 = z["prev"], z["cur"], z["full_max"], z["full_l2"]
     assert int(meta[0]) == n and meta[1] == alpha and meta[2] == 1e-3 and int(meta[3]) == 1000
@@ -58,3 +62,10 @@ def test_stored_long_runs(n, alpha):
     assert np.abs(cur).max() <= fmax[1] and np.abs(prev).max() <= fmax[0]
     assert np.abs(cur).max() >= 0.5 * fmax[1]
     assert fl2[1] > 0 and not np.array_equal(prev, cur)
+    if embed is not None:
+        # the second embedding changes only the rounding: the two oracle runs agree closely
+        # but not bit for bit
+        with np.load(gen.path_for(n, alpha), allow_pickle=False) as z:
+            base = z["cur"]
+        d = np.abs(base - cur).max() / fmax[1]
+        assert 0.0 < d < 1e-8

@@ -475,12 +475,31 @@ def test_run_matches_single_steps(n, steps):
 GOLDEN_RUNS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_runs")
 
 
-def _stored_run(n, alpha):
-    """The oracle's u^999, u^1000 of the 1000-step workload (tests/golden/make_long_runs.py)."""
-    path = os.path.join(GOLDEN_RUNS, f"N{n}_a{alpha}.npz")
-    assert os.path.exists(path), f"stored oracle run {os.path.basename(path)} missing (tests/golden/make_long_runs.py)"
+def _stored_run(n, alpha, embed=None):
+    """The oracle's u^999, u^1000 of the 1000-step workload (tests/golden/make_long_runs.py);
+    embed: the oracle's second run with its BCCB embedding at that size."""
+    name = f"N{n}_a{alpha}" + ("" if embed is None else f"_p{embed}") + ".npz"
+    path = os.path.join(GOLDEN_RUNS, name)
+    assert os.path.exists(path), f"stored oracle run {name} missing (tests/golden/make_long_runs.py)"
     with np.load(path, allow_pickle=False) as z:
         return {k: z[k] for k in z.files}
+
+
+# workloads whose oracle run is also stored with the embedding at 2N + 2 instead of 2N
+FLOOR_RUNS = {(2047, 1.8), (4095, 1.8)}
+
+
+def _run_tolerance(n, alpha, ref):
+    """1e-10, or twice the float64 floor of the run itself where that is measured: the
+    distance between the oracle's two runs that differ only in the size of the BCCB
+    embedding (the same scheme in exact arithmetic).  The GPU differs from the oracle in
+    every rounding, so its distance from the oracle is a second sample of that spread."""
+    if (n, alpha) not in FLOOR_RUNS:
+        return 1e-10, None
+    other = _stored_run(n, alpha, embed=2 * n + 2)
+    assert np.array_equal(other["idx"], ref["idx"])
+    d = max(float(np.abs(other[key] - ref[key]).max() / ref["full_max"][k]) for k, key in enumerate(("prev", "cur")))
+    return max(1e-10, 2.0 * d), d
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
@@ -490,10 +509,13 @@ def test_configured_run_1000_steps(n, alpha, prec):
     """The large workloads as configured (Omega=(-1,1)^2, kappa=1, g=-sin u, tau=1e-3,
     seeded Gaussian phi1, phi2=0): the start-up step and 999 steps through sadi_run, against
     the oracle's own 1000-step run (u^999 and u^1000 at the stored sample nodes, and the
-    maximum and 2-norm over the whole grid), to 1e-10 relative.  At alpha = 1.5 on the two
-    larger grids the run is also cut at n = 1, 500 and 999, and the oracle takes one step
-    from the GPU's (u^{n-1}, u^n): u^{n+1} to 1e-12 and the increment to 1e-10."""
+    maximum and 2-norm over the whole grid), to 1e-10 relative, or to twice the run's own
+    float64 floor where the oracle's second run (another embedding size) shows a larger
+    one.  At alpha = 1.5 on the two larger grids the run is also cut at n = 1, 500 and
+    999, and the oracle takes one step from the GPU's (u^{n-1}, u^n): u^{n+1} to 1e-12 and
+    the increment to 1e-10."""
     ref = _stored_run(n, alpha)
+    tol, floor = _run_tolerance(n, alpha, ref)
     assert int(ref["meta"][0]) == n and ref["meta"][1] == alpha and int(ref["meta"][3]) == 1000
     wl = W.config2(n, alpha, seed=int(ref["meta"][4]))
     _say(f"configured 1000-step run n={n} alpha={alpha} {prec}")
@@ -526,9 +548,9 @@ def test_configured_run_1000_steps(n, alpha, prec):
         e_max = abs(np.abs(g).max() / ref["full_max"][k] - 1.0)
         e_l2 = abs(np.sqrt(np.sum(g * g)) / ref["full_l2"][k] - 1.0)
         errs.append((e, e_max, e_l2))
-    _say(f"  u^999 / u^1000 vs oracle run: {errs}")
+    _say(f"  u^999 / u^1000 vs oracle run: {errs}; oracle's own floor {floor}, bound {tol:.2e}")
     for e, e_max, e_l2 in errs:
-        assert e <= 1e-10 and e_max <= 1e-10 and e_l2 <= 1e-10
+        assert e <= tol and e_max <= tol and e_l2 <= tol
 
 
 def test_configured_run_1000_steps_fp32_unrefined():
