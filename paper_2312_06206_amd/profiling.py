@@ -208,3 +208,55 @@ def valu_for(kernel: str, workload: str = "N4095"):
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("kernels", {}).get(kernel)
+
+
+MFMA_PEAK_TFLOPS = {"double": 78.6, "float": 157.3}   # MI355X dense matrix-core peaks
+
+
+def write_mfma_summary(pmc_dir: str, out_md: str, command: str) -> list:
+    """Matrix-core use of every product kernel dispatch in one rocprofv3 --pmc run of
+    SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32 (units of 512 flops): dispatches grouped by kernel,
+    work-items and flops, with the achieved rate from each dispatch's own start and end times
+    against the dense peak of its operand type."""
+    import csv
+    per: dict = {}
+    with open(find_csv(pmc_dir)) as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            if "gemm_mfma_kernel" not in name:
+                continue
+            d = per.setdefault(row["Dispatch_Id"], {"name": name, "items": int(row["Grid_Size"]),
+                                                    "ns": float(row["End_Timestamp"]) - float(row["Start_Timestamp"])})
+            d[row["Counter_Name"]] = float(row["Counter_Value"])
+    groups: dict = {}
+    for d in per.values():
+        ti = "float" if "gemm_mfma_kernel<float" in d["name"] else "double"
+        mops = d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) + d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+        flops = 512.0 * mops
+        short = d["name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("sadi::", "")
+        key = (short, d["items"], round(flops / 1e6))
+        g = groups.setdefault(key, {"kernel": short, "type": ti, "work_items": d["items"], "flops": flops,
+                                    "calls": 0, "ns": 0.0, "busy": 0.0, "gui": 0.0})
+        g["calls"] += 1
+        g["ns"] += d["ns"]
+        g["busy"] += d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        g["gui"] += d.get("GRBM_GUI_ACTIVE", 0.0)
+    out = []
+    for g in groups.values():
+        avg_us = g["ns"] / g["calls"] / 1e3
+        tf = g["flops"] / (avg_us * 1e-6) / 1e12 if avg_us > 0 else 0.0
+        out.append(dict(g, avg_us=avg_us, tflops=tf, frac=tf / MFMA_PEAK_TFLOPS[g["type"]]))
+    out.sort(key=lambda g: -g["flops"] * g["calls"])
+    lines = ["# Matrix-core use of the product kernels", "", "Command (from the repository root):", "",
+             "```", command, "```", "",
+             "Rate = flops from SQ_INSTS_VALU_MFMA_MOPS_* (x 512) over each dispatch's own duration in the "
+             "counter run; peak = MI355X dense matrix-core rate of the operand type (FP64 78.6, FP32 157.3 "
+             "TFLOP/s).", "",
+             "| kernel | calls | work-items | GFLOP per call | avg us | TFLOP/s | % of peak |",
+             "|---|---|---|---|---|---|---|"]
+    for g in out:
+        lines.append(f"| `{g['kernel'][:60]}` | {g['calls']} | {g['work_items']} | {g['flops'] / 1e9:.3f} | "
+                     f"{g['avg_us']:.1f} | {g['tflops']:.1f} | {100 * g['frac']:.1f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
