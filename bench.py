@@ -384,6 +384,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient (adjoint) leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own workloads")
     ap.add_argument("--no-sweep", action="store_true", help="skip the N x alpha sweep of the FP64 configuration")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the 1000-step runs compared with the oracle's stored run")
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed runs of K steps, reported with their median beside value")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -482,7 +484,7 @@ def main():
                               "steps": steps + args.warmup + 1}
         s.set_options(wl.g, 0.0, "fp64")
     # every precision against the oracle's own 1000-step run of this workload
-    ref = stored_oracle_run(wl.n, wl.alpha, args.seed)
+    ref = None if args.no_accuracy else stored_oracle_run(wl.n, wl.alpha, args.seed)
     oracle_errs = None
     if ref is not None:
         oracle_errs = oracle_run_errors(s, wl, ref, ["fp64"] + list(variants))
