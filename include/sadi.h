@@ -73,13 +73,17 @@ typedef enum {
 
 /* Create a context for (alpha, kappa, N, tau, Omega = (domain[0], domain[1])^2).
  * Validates 1 < alpha < 2, kappa > 0, tau > 0, domain[1] > domain[0] (all finite).
- * Computes on the host: the 1D coefficients a_k (closed form, section 2), the 2D
- * coefficients a_ij of L_h (Fourier coefficients of the symbol), the generating
- * vector H_M^-1 e_1 of the size-M line matrix and its circulant / skew-circulant
- * eigenvalues (Proposition 1), and the eigenvalues of the block-circulant
- * embedding of L_h; uploads them and allocates the device workspaces.  Uses the
- * current HIP device.  Host-synchronous.  Defaults: g = -sin u, float64.
- * domain: host pointer to 2 doubles.  *out receives the context (NULL on error). */
+ * Computes the 1D coefficients a_k (closed form, section 2; host, extended precision),
+ * the 2D coefficients a_ij of L_h (Fourier coefficients of the symbol by a quadrature of
+ * its subordination integral: Bessel node rows from a per-device table, two matrix-core
+ * products on the device, an exact low-order corner from the host), the generating vector
+ * H_M^-1 e_1 of the size-M line matrix and its circulant / skew-circulant eigenvalues
+ * (Proposition 1; on the device in double-double arithmetic when N + 1 = M, else on the
+ * host in extended precision with the rank-(M - N) correction), and the eigenvalues of
+ * the block-circulant embedding of L_h (device).  Allocates the device workspaces in one
+ * block.  Uses the current HIP device; the device work runs on streams of its own.
+ * Host-synchronous.  Defaults: g = -sin u, float64.  domain: host pointer to 2 doubles.
+ * *out receives the context (NULL on error). */
 sadi_status sadi_setup(double alpha, double kappa, int n, double tau, const double* domain, sadi_ctx** out);
 
 /* Same, with caller-supplied coefficient tables instead of the computed ones
