@@ -46,7 +46,7 @@ def _generator():
 @pytest.mark.parametrize("n,alpha,embed", [(1023, 1.2, None), (1023, 1.5, None), (1023, 1.8, None),
                                            (2047, 1.2, None), (2047, 1.5, None), (2047, 1.8, None),
                                            (4095, 1.2, None), (4095, 1.5, None), (4095, 1.8, None),
-                                           (2047, 1.8, 4096), (4095, 1.8, 8192)])
+                                           (2047, 1.8, 4096), (4095, 1.5, 8192), (4095, 1.8, 8192)])
 def test_stored_long_runs(n, alpha, embed):
     gen = _generator()
     path = gen.path_for(n, alpha, embed)

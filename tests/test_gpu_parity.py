@@ -486,7 +486,7 @@ def _stored_run(n, alpha, embed=None):
 
 
 # workloads whose oracle run is also stored with the embedding at 2N + 2 instead of 2N
-FLOOR_RUNS = {(2047, 1.8), (4095, 1.8)}
+FLOOR_RUNS = {(2047, 1.8), (4095, 1.5), (4095, 1.8)}
 
 
 def _run_tolerance(n, alpha, ref):
