@@ -1092,7 +1092,7 @@ rows_rhs_gs_batched(const BatchInst* __restrict__ bi, int iu, int lds_, int ldx,
   __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
-  rows_rhs_gs_body<M, MODE, 0>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M,
+  rows_rhs_gs_body<M, MODE, MODE == 0 ? 1 : 0>(p.S, lds_, p.u[iu], n, p.phi2, p.X, ldx, n, p.sc, tab, gs, tab.root2M,
                                rhs_row_block<M>(), smem);
 }
 
@@ -1130,7 +1130,7 @@ cols_gs_fwd_batched(const BatchInst* __restrict__ bi, int ic, int ip, int ldx, i
   if (grp >= ngroups) return;   // whole workgroup
   const BatchInst& p = bi[blockIdx.y];
   const GSTables64 gs{tab.root2M, p.lam_s, p.lam_c, p.f, p.r};
-  cols_gs_fwd_body<M, 0>(p.X, ldx, p.u[ic], p.u[ip], n, p.S, lds_, tab, gs, tab.root2M, grp, 1, smem);
+  cols_gs_fwd_body<M, 1>(p.X, ldx, p.u[ic], p.u[ip], n, p.S, lds_, tab, gs, tab.root2M, grp, 1, smem);
 }
 
 // ----------------------------------------------------------------------------------
@@ -1186,7 +1186,7 @@ rows_rhs_gs_worklist(const BatchInst* __restrict__ bi, const WorkItem* __restric
   switch (p.m) {
 #define SADI_WL_ROW(MM)                                                                              \
   case MM:                                                                                           \
-    rows_rhs_gs_body<MM, 0, 0>(p.S, p.lds, p.u[iu], p.n, p.phi2, p.X, p.ldx, p.n, p.sc, p.tab, gs,   \
+    rows_rhs_gs_body<MM, 0, 1>(p.S, p.lds, p.u[iu], p.n, p.phi2, p.X, p.ldx, p.n, p.sc, p.tab, gs,   \
                                p.tab.root2M, w.blk, smem);                                           \
     break;
     SADI_WL_CASES(SADI_WL_ROW)
@@ -1205,7 +1205,7 @@ cols_gs_fwd_worklist(const BatchInst* __restrict__ bi, const WorkItem* __restric
   switch (p.m) {
 #define SADI_WL_GS(MM)                                                                              \
   case MM:                                                                                          \
-    cols_gs_fwd_body<MM, 0>(p.X, p.ldx, p.u[ic], p.u[ip], p.n, p.S, p.lds, p.tab, gs, p.tab.root2M, \
+    cols_gs_fwd_body<MM, 1>(p.X, p.ldx, p.u[ic], p.u[ip], p.n, p.S, p.lds, p.tab, gs, p.tab.root2M, \
                             w.blk, 1, smem);                                                        \
     break;
     SADI_WL_CASES(SADI_WL_GS)
