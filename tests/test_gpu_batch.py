@@ -165,3 +165,29 @@ def test_batch_at_the_benchmark_sizes(schedule):
             ref_prev, ref_cur = reference(m, 5)
             assert rel(from_dev(u1[k]), ref_cur) < 1e-11, (k, m.n)
             assert rel(from_dev(u0[k]), ref_prev) < 1e-11, (k, m.n)
+
+
+@pytest.mark.parametrize("path", ["fft_gs", "dense"])
+def test_batch_general_n(path):
+    """Members whose N + 1 is not a power of two (the line solves' rank-(M - N) correction,
+    ranks 2, 12 and 28 here, applied per line inside the batched kernels), on both paths,
+    under graph replay, against the oracle after 7 steps."""
+    from paper_2312_06206_amd import Batch
+    _dev()
+    ms = W.batch_members(6, seed=5, n_choices=(20, 62, 100))
+    _say(f"batch general N: {[m.n for m in ms]} path={path}")
+    b = Batch([m.n for m in ms], [m.alpha for m in ms], [m.kappa for m in ms], TAU, dense_max_n=127)
+    for n in sorted({m.n for m in ms}):
+        b.set_path(n, path)
+    b.set_graph(True)
+    u0 = [to_dev(m.phi1()) for m in ms]
+    u1 = [torch.zeros_like(t) for t in u0]
+    p2 = [to_dev(0.3 * W.asymmetric_field(m.n, seed=m.n)) for m in ms]
+    b.bind(u0, u1, p2)
+    with b:
+        b.first_step()
+        b.run(6)
+        for k, m in enumerate(ms):
+            ref_prev, ref_cur = reference(m, 7)
+            assert rel(from_dev(u1[k]), ref_cur) < 1e-11, (k, m.n)
+            assert rel(from_dev(u0[k]), ref_prev) < 1e-11, (k, m.n)
