@@ -89,6 +89,36 @@ void* resolve_scratch(int dev) {
   return g_scratch_addr[dev];
 }
 
+// Streams for set-up work, per device: taken for the length of one set-up and returned, so
+// that contexts set up one after another (or on a pool of host threads) reuse them instead
+// of creating and destroying two streams each.  Kept until the process ends; at most as
+// many as set-ups ran at once.
+std::mutex g_setup_stream_mutex;
+std::vector<hipStream_t> g_setup_streams[kMaxDevices];
+
+hipError_t take_setup_stream(int dev, hipStream_t* s) {
+  if (dev >= 0 && dev < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_setup_stream_mutex);
+    if (!g_setup_streams[dev].empty()) {
+      *s = g_setup_streams[dev].back();
+      g_setup_streams[dev].pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+// s must be idle (synchronised) when it is returned
+void return_setup_stream(int dev, hipStream_t s) {
+  if (!s) return;
+  if (dev >= 0 && dev < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_setup_stream_mutex);
+    g_setup_streams[dev].push_back(s);
+    return;
+  }
+  (void)hipStreamDestroy(s);
+}
+
 // bytes of the step's work space in the static array: S (rows in pairs), 256-byte aligned,
 // then X
 size_t noalloc_s_bytes(const sadi_ctx* c) {
@@ -439,20 +469,22 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     }
     SADI_HIP_OR(hipMemcpy(pool, host.data(), staged, hipMemcpyHostToDevice), bail);
   }
-  // set-up work runs on a stream of its own (contexts set up concurrently on several host
+  // set-up work runs on streams of its own (contexts set up concurrently on several host
   // threads overlap on the device), synchronised before returning
+  int sdev = 0;
+  if (hipGetDevice(&sdev) != hipSuccess) sdev = -1;
   hipStream_t sst = nullptr, sgs = nullptr;
-  SADI_HIP_OR(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking), bail);
+  SADI_HIP_OR(take_setup_stream(sdev, &sst), bail);
   auto bail_s = [&](sadi_status e) {
     for (hipStream_t q : {sst, sgs})
       if (q) {
         (void)hipStreamSynchronize(q);
-        (void)hipStreamDestroy(q);
+        (void)hipStreamDestroy(q);   // not returned: the stream may hold a failed launch
       }
     return bail(e);
   };
   if (device_gs) {   // c = H_M^-1 e_1 (one workgroup, sequential in k), then the tables
-    SADI_HIP_OR(hipStreamCreateWithFlags(&sgs, hipStreamNonBlocking), bail_s);
+    SADI_HIP_OR(take_setup_stream(sdev, &sgs), bail_s);
     sadi::launch_gs_generator((const double*)(pool + o_thi), (const double*)(pool + o_tlo), m,
                               (double*)(pool + o_cvec), c->root2M, c->lam_s, c->lam_c, c->f, c->lam_s32, c->lam_c32,
                               c->f32, sgs);
@@ -493,8 +525,8 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
     SADI_HIP_OR(hipGetLastError(), bail_s);
     SADI_HIP_OR(hipStreamSynchronize(sst), bail_s);
     if (sgs) SADI_HIP_OR(hipStreamSynchronize(sgs), bail_s);
-    SADI_HIP_OR(hipStreamDestroy(sst), bail);
-    if (sgs) SADI_HIP_OR(hipStreamDestroy(sgs), bail);
+    return_setup_stream(sdev, sst);
+    return_setup_stream(sdev, sgs);
   }
   // the static work space of sadi_step_noalloc on this device
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SADI_E_DEVICE, "hipGetDevice"));
