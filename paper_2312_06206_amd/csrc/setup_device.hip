@@ -142,17 +142,20 @@ __host__ __device__ inline DD dd_recip(DD a) {
 constexpr int kLevThreads = 1024;
 constexpr int kLevMaxM = 4096;
 
-// sum of v over the workgroup (red: kLevThreads / 64 entries of LDS); every thread adds the
-// waves' partial sums itself, in the same order, so all get the same total after one
-// barrier.  The caller synchronises before red is written again.
+// sum of v over the workgroup (red: kLevThreads / 64 entries of LDS).  After one barrier
+// every wave reduces the waves' partial sums itself (a butterfly over groups of lanes) and
+// takes lane 0's result, so all threads get the same total.  The caller synchronises
+// before red is written again.
 __device__ DD block_sum_dd(DD v, DD* red) {
+  constexpr int W = kLevThreads / 64;
+  static_assert((W & (W - 1)) == 0 && W <= 64, "waves per workgroup: a power of two");
   for (int off = 32; off > 0; off >>= 1) v = dd_add(v, DD{__shfl_down(v.hi, off), __shfl_down(v.lo, off)});
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  DD tot = red[0];
+  DD p = red[threadIdx.x & (W - 1)];
 #pragma unroll
-  for (int w = 1; w < kLevThreads / 64; ++w) tot = dd_add(tot, red[w]);
-  return tot;
+  for (int off = W / 2; off > 0; off >>= 1) p = dd_add(p, DD{__shfl_xor(p.hi, off), __shfl_xor(p.lo, off)});
+  return DD{__shfl(p.hi, 0), __shfl(p.lo, 0)};
 }
 
 // Levinson-Durbin recursion for T c = e_1, T the SPD Toeplitz matrix of first column t (given

@@ -604,4 +604,4 @@ def test_device_line_tables_match_host(n, alpha):
     for name, d, h in (("lam_s", ls_d, ls_h), ("lam_c", lc_d, lc_h), ("f", f_d, f_h)):
         err = np.abs(d - h).max() / np.abs(h).max()
         _say(f"  {name}: {err:.2e}")
-        assert err <= 1e-14, name
+        assert err <= 1e-15, name     # measured <= 2.3e-16 up to N = 4095
