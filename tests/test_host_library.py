@@ -88,9 +88,34 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu(args, status):
 def test_calls_on_null_context_fail_with_state_error():
     lib = P.load_library()
     assert lib.sadi_step(None, None, None) == -5
+    assert lib.sadi_step_noalloc(None, None, None) == -5
     assert lib.sadi_run(None, None, None, 1) == -5
+    assert lib.sadi_first_step(None, None, None, None) == -5
     assert lib.sadi_toeplitz_solve(None, None, 1, 1) == -5
+    assert lib.sadi_apply_lh(None, None, None) == -5
+    assert lib.sadi_get_line_tables(None, None, None, None) == -5
+    assert lib.sadi_get_info(None, None, None, None) == -5
     assert lib.sadi_destroy(None) == 0
+    assert lib.sadi_batch_get_group(None, 0, None, None, None, None, None, None, None) == -5
+    assert lib.sadi_batch_set_path(None, 63, 2) == -5
+    assert lib.sadi_batch_tune(None, 1) == -5
+
+
+def test_host_line_tables_match_dense_solve():
+    """sadi_host_line_tables (the host reference of the device tables): lam_c = fft(c) / M
+    and f[k] = c[M-1-k] / c[0] for c = H_M^-1 e_1 from a dense solve, at N = 63 (M = 64)."""
+    alpha, kappa, n, tau = 1.6, 1.0, 63, 1e-2
+    ls, lc, f = P.host_line_tables(alpha, kappa, n, tau)
+    m = n + 1
+    h = 2.0 / (n + 1)
+    H = np.eye(m) + 0.5 * kappa * tau * tau * h ** (-alpha) * scipy.linalg.toeplitz(C.riesz_coeffs(alpha, m))
+    c = scipy.linalg.solve(H, np.eye(m)[:, 0], assume_a="pos")
+    assert np.abs(lc - np.fft.fft(c) / m).max() <= 1e-15 * np.abs(lc).max()
+    assert np.abs(f - c[m - 1 - np.arange(n)] / c[0]).max() <= 1e-15 * np.abs(f).max()
+    # lam_s = fft(Q s) / (2 p1 M), s = (p1, -c[M-1], ..., -c[1]), Q = diag(e^{-i pi j / M})
+    sv = np.concatenate(([c[0]], -c[:0:-1]))
+    q = np.exp(-1j * np.pi * np.arange(m) / m)
+    assert np.abs(ls - np.fft.fft(q * sv) / (2 * c[0] * m)).max() <= 1e-15 * np.abs(ls).max()
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
