@@ -160,12 +160,14 @@ __device__ DD block_sum_dd(DD v, DD* red) {
 
 // Levinson-Durbin recursion for T c = e_1, T the SPD Toeplitz matrix of first column t (given
 // as double-double t_hi + t_lo, m <= 4096 entries), in double-double arithmetic by one
-// workgroup: with f the solution at size k, e = sum_{i<k} t[k-i] f[i] and [f; 0] updated to
-// ([f; 0] - e [0; J f]) / (1 - e^2), pairs (i, k - i) in place.  c = f rounded to float64.
+// workgroup: with f the solution at size k (T_k f = e_1), e = sum_{i<k} t[k-i] f[i] and
+// [f; 0] updated to ([f; 0] - e [0; J f]) / (1 - e^2), pairs (i, k - i) in place.  The
+// thread that forms the new f[i] also adds its terms of the next e, so each step needs one
+// barrier (the block sum's; its partials alternate between two buffers).  c = f rounded.
 __global__ void __launch_bounds__(kLevThreads)
 levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo, int m, double* __restrict__ c) {
   __shared__ double fh[kLevMaxM], fl[kLevMaxM], th[kLevMaxM], tl[kLevMaxM];
-  __shared__ DD red[kLevThreads / 64];
+  __shared__ DD red[2][kLevThreads / 64];
   for (int i = threadIdx.x; i < m; i += kLevThreads) {
     th[i] = t_hi[i];
     tl[i] = t_lo[i];
@@ -173,18 +175,18 @@ levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo
     fl[i] = 0.0;
   }
   __syncthreads();
+  DD acc{0.0, 0.0};   // this thread's terms of the next e
   if (threadIdx.x == 0) {
     const DD f0 = dd_recip(DD{th[0], tl[0]});
     fh[0] = f0.hi;
     fl[0] = f0.lo;
+    if (m > 1) acc = dd_mul(DD{th[1], tl[1]}, f0);
   }
-  __syncthreads();
   for (int k = 1; k < m; ++k) {
-    DD acc{0.0, 0.0};
-    for (int i = threadIdx.x; i < k; i += kLevThreads)
-      acc = dd_add(acc, dd_mul(DD{th[k - i], tl[k - i]}, DD{fh[i], fl[i]}));
-    const DD e = block_sum_dd(acc, red);
+    const DD e = block_sum_dd(acc, red[k & 1]);
     const DD inv = dd_recip(dd_sub(DD{1.0, 0.0}, dd_mul(e, e)));
+    acc = DD{0.0, 0.0};
+    const bool next = k + 1 < m;
     for (int i = threadIdx.x; 2 * i <= k; i += kLevThreads) {
       const int j = k - i;                       // f[k] is still 0 here
       const DD a{fh[i], fl[i]}, b{fh[j], fl[j]};
@@ -192,13 +194,15 @@ levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo
       const DD nb = dd_mul(dd_sub(b, dd_mul(e, a)), inv);
       fh[i] = na.hi;
       fl[i] = na.lo;
+      if (next) acc = dd_add(acc, dd_mul(DD{th[k + 1 - i], tl[k + 1 - i]}, na));
       if (j != i) {
         fh[j] = nb.hi;
         fl[j] = nb.lo;
+        if (next) acc = dd_add(acc, dd_mul(DD{th[i + 1], tl[i + 1]}, nb));
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int i = threadIdx.x; i < m; i += kLevThreads) c[i] = fh[i] + fl[i];
 }
 
