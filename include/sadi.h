@@ -250,8 +250,9 @@ typedef enum { SADI_PATH_FFT_GS = 0, SADI_PATH_DENSE = 1, SADI_PATH_DENSE_MIXED 
 
 /* count instances; n, alpha, kappa: host arrays of count entries (each validated as in
  * sadi_setup); tau and domain (host, 2 doubles) are shared.  Groups with N <= dense_max_n
- * also get the explicit inverse (N*N doubles per instance), its FP32 copy and H itself
- * (N*N floats and doubles) for the two dense paths.
+ * may take the two dense paths; their explicit inverses (N*N doubles per instance) and,
+ * for SADI_PATH_DENSE_MIXED, the FP32 copies and H itself (N*N floats and doubles) are
+ * built when a dense path is first timed (sadi_batch_tune) or chosen (sadi_batch_set_path).
  * Host-synchronous; allocates everything the batch needs.  All groups start on
  * SADI_PATH_FFT_GS. */
 sadi_status sadi_batch_create(int count, const int* n, const double* alpha, const double* kappa, double tau,

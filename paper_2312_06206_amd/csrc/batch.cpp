@@ -43,6 +43,7 @@ struct Group {
   sadi::CvtPtrs* d_cvt = nullptr;             // X32 = (float) X
   sadi::CopyPtrs* d_copy = nullptr;           // X = Y
   bool mixed_ready = false;                   // the above built (setup_mixed)
+  bool dense_ready = false;                   // hinv, d_prod1, d_prod2 built (setup_dense)
 };
 
 bool dense_path(int path) { return path == SADI_PATH_DENSE || path == SADI_PATH_DENSE_MIXED; }
@@ -52,6 +53,7 @@ bool dense_path(int path) { return path == SADI_PATH_DENSE || path == SADI_PATH_
 struct sadi_batch {
   int magic = 0x5AD2;
   int count = 0;
+  int dense_max_n = 0;                        // groups up to this N may take the dense paths
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
   std::vector<sadi_ctx*> ctx;
@@ -164,12 +166,48 @@ sadi_status mixed_sweeps(sadi_batch* b, const Group& g) {
   return check_launch();
 }
 
+bool dense_ok(const sadi_batch* b, const Group& g) { return g.n <= b->dense_max_n; }
+
+// The explicit H^-1 of every member of a group (rows H^-1 e_k: the line solve applied to
+// the rows of an identity written on the device, on the batch's stream, in one allocation
+// for the group) and the pointer triples of dense_sweeps; built on first use (the tuner or
+// sadi_batch_set_path).
+sadi_status setup_dense(sadi_batch* b, Group& g) {
+  if (g.dense_ready || !dense_ok(b, g)) return SADI_OK;
+  const size_t cnt = g.members.size(), nn = (size_t)g.n * g.n;
+  sadi_status st;
+  double* pool = nullptr;
+  if ((st = b->alloc((void**)&pool, sizeof(double) * nn * cnt)) != SADI_OK) return st;
+  std::vector<double*> hinv(cnt);
+  std::vector<sadi::GemmPtrs> p1(cnt), p2(cnt);
+  for (size_t k = 0; k < cnt; ++k) {
+    sadi_ctx* c = b->ctx[g.members[k]];
+    hinv[k] = pool + nn * k;
+    sadi::launch_identity(hinv[k], g.n, b->stream);
+    if ((st = sadi_toeplitz_solve(c, hinv[k], g.n, g.n)) != SADI_OK) return st;
+    double* t = reinterpret_cast<double*>(c->S);   // N x ldX doubles fit in the spectrum buffer
+    p1[k] = sadi::GemmPtrs{c->X, hinv[k], t};
+    p2[k] = sadi::GemmPtrs{hinv[k], t, c->X};
+  }
+  const size_t pb = sizeof(sadi::GemmPtrs) * cnt;
+  if ((st = b->alloc((void**)&g.d_prod1, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_prod2, pb)) != SADI_OK)
+    return st;
+  if (hipMemcpy(g.d_prod1, p1.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g.d_prod2, p2.data(), pb, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SADI_E_DEVICE, "hipMemcpy");
+  g.hinv.swap(hinv);
+  g.dense_ready = true;
+  return check_launch();
+}
+
 // Data of SADI_PATH_DENSE_MIXED for a group with explicit inverses, built on first use (the
 // tuner or sadi_batch_set_path): H^-1 rounded to FP32, H itself in FP64 (from its first
 // column, formed on the host exactly as the line tables' generating column), and the
 // pointer arrays of mixed_sweeps.
 sadi_status setup_mixed(sadi_batch* b, Group& g) {
-  if (g.mixed_ready || g.hinv.empty()) return SADI_OK;
+  if (g.mixed_ready || !dense_ok(b, g)) return SADI_OK;
+  sadi_status st0 = setup_dense(b, g);
+  if (st0 != SADI_OK) return st0;
   const size_t cnt = g.members.size(), nn = (size_t)g.n * g.n;
   sadi_status st;
   float* pool32 = nullptr;
@@ -482,6 +520,7 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
     return fail(st, msg);
   };
   b->count = count;
+  b->dense_max_n = dense_max_n;
   b->ctx.assign(count, nullptr);
   {
     // instances set up concurrently, one host thread each
@@ -544,29 +583,6 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
     sadi_status st;
     if ((st = b->alloc((void**)&g.d_inst, sizeof(sadi::BatchInst) * cnt)) != SADI_OK) return bail(st);
     if ((st = b->alloc((void**)&g.d_scratch_inst, sizeof(sadi::BatchInst) * cnt)) != SADI_OK) return bail(st);
-    if (g.n > dense_max_n) continue;
-    // explicit H^-1 of every member: the line solve applied to the rows of the identity,
-    // both on the batch's stream
-    const size_t nn = (size_t)g.n * g.n;
-    g.hinv.resize(cnt);
-    double* pool = nullptr;   // one allocation for the group
-    if ((st = b->alloc((void**)&pool, sizeof(double) * nn * cnt)) != SADI_OK) return bail(st);
-    std::vector<sadi::GemmPtrs> p1(cnt), p2(cnt);
-    for (size_t k = 0; k < cnt; ++k) {
-      sadi_ctx* c = b->ctx[g.members[k]];
-      g.hinv[k] = pool + nn * k;
-      sadi::launch_identity(g.hinv[k], g.n, b->stream);
-      if ((st = sadi_toeplitz_solve(c, g.hinv[k], g.n, g.n)) != SADI_OK) return bail(st);
-      double* t = reinterpret_cast<double*>(c->S);   // N x ldX doubles fit in the spectrum buffer
-      p1[k] = sadi::GemmPtrs{c->X, g.hinv[k], t};
-      p2[k] = sadi::GemmPtrs{g.hinv[k], t, c->X};
-    }
-    const size_t pb = sizeof(sadi::GemmPtrs) * cnt;
-    if ((st = b->alloc((void**)&g.d_prod1, pb)) != SADI_OK || (st = b->alloc((void**)&g.d_prod2, pb)) != SADI_OK)
-      return bail(st);
-    if (hipMemcpy(g.d_prod1, p1.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g.d_prod2, p2.data(), pb, hipMemcpyHostToDevice) != hipSuccess)
-      return bail(fail(SADI_E_DEVICE, "hipMemcpy"));
   }
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(SADI_E_DEVICE, "setup synchronisation"));
   *out = b;
@@ -640,10 +656,10 @@ sadi_status sadi_batch_set_path(sadi_batch* b, int n, int path) {
   if (path != SADI_PATH_FFT_GS && !dense_path(path)) return fail(SADI_E_INVALID, "unknown path");
   for (Group& g : b->groups) {
     if (g.n != n) continue;
-    if (dense_path(path) && g.hinv.empty())
+    if (dense_path(path) && !dense_ok(b, g))
       return fail(SADI_E_UNSUPPORTED, "no explicit inverse for N = " + std::to_string(n) + " (above dense_max_n)");
-    if (path == SADI_PATH_DENSE_MIXED) {
-      const sadi_status st = setup_mixed(b, g);
+    if (dense_path(path)) {
+      const sadi_status st = path == SADI_PATH_DENSE ? setup_dense(b, g) : setup_mixed(b, g);
       if (st != SADI_OK) return st;
     }
     g.path = path;
@@ -715,7 +731,7 @@ sadi_status sadi_batch_tune(sadi_batch* b, int steps) {
                                 {SADI_PATH_DENSE_MIXED, 64}, {SADI_PATH_DENSE_MIXED, 32}};
     for (int v = 0; v < 5 && st == SADI_OK; ++v) {
       const int path = variants[v][0];
-      if (dense_path(path) && all[gi].hinv.empty()) continue;
+      if (dense_path(path) && !dense_ok(b, all[gi])) continue;
       b->groups[0].path = path;
       b->groups[0].tile[path] = variants[v][1];
       st = batch_run(b, true, 2, false);   // warm-up
