@@ -127,11 +127,12 @@ sadi_status sadi_step(sadi_ctx* ctx, double* u_prev, const double* u_cur);
 sadi_status sadi_step_noalloc(sadi_ctx* ctx, double* u_prev, const double* u_cur);
 
 /* nsteps >= 0 steps n >= 1.  On entry (u_prev, u_cur) = (u^{n-1}, u^n); on exit
- * (u_prev, u_cur) = (u^{n+nsteps-1}, u^{n+nsteps}).  Both arrays are work space while
- * the calls run: unless the correction rank M - N exceeds 3, the steps alternate between
- * the grid and its transpose (the scheme is symmetric in x and y), with one in-place
- * transpose before the first step and one transpose or transposing exchange after the
- * last, in every precision.  The result matches nsteps calls of sadi_step to rounding. */
+ * (u_prev, u_cur) = (u^{n+nsteps-1}, u^{n+nsteps}).  Unless the correction rank M - N
+ * exceeds 3, the steps alternate between the grid and its transpose (the scheme is
+ * symmetric in x and y), in every precision: the state is copied into the context's own
+ * arrays (in pairs of rows, u^{n-1} transposed) before the first step and back after the
+ * last, and u_prev is read only there.  Above rank 3 both arrays are work space while the
+ * calls run.  The result matches nsteps calls of sadi_step to rounding. */
 sadi_status sadi_run(sadi_ctx* ctx, double* u_prev, double* u_cur, int nsteps);
 
 /* In place, lines[r*ld + i] <- (H^-1 v_r)_i for r < nlines, i < N, where v_r is

@@ -536,6 +536,7 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
       pool.emplace_back([&, w] {
         (void)hipSetDevice(device);   // the caller's device, as for sadi_setup
         g_setup_threads = inner;
+        g_setup_no_run_state = true;   // batch members take batched steps only
         for (int i = w; i < count; i += workers) {
           status[i] = sadi_setup(alpha[i], kappa[i], n[i], tau, domain, &b->ctx[i]);
           if (status[i] != SADI_OK) errors[i] = sadi_last_error();

@@ -20,6 +20,8 @@ bool finite_all(std::initializer_list<double> v);
 bool supported_n(int n);
 // host threads for the set-up maths of the calling thread (0: all hardware threads)
 extern thread_local int g_setup_threads;
+// set-up on this thread skips the run state buffers (contexts that only take batched steps)
+extern thread_local bool g_setup_no_run_state;
 // argument checks of sadi_setup (allow2: alpha = 2 accepted, for injected tables)
 sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2);
 }  // namespace sadi_impl
@@ -81,6 +83,9 @@ struct sadi_ctx {
   double* sig_e = nullptr;
   double* sig_o = nullptr;
   double* partial = nullptr;   // 4 N partial sums (adjoint inner products)
+  // sadi_run's copies of the two state arrays in paired rows (N + 1 rows of pitch N each),
+  // or null (the run then works on the caller's arrays in plain rows)
+  double* run_state[2] = {nullptr, nullptr};
   // device the context was set up on, and that device's static work space of
   // sadi_step_noalloc (null if its address could not be resolved)
   int device = 0;

@@ -553,7 +553,7 @@ __device__ __forceinline__ void cols_conv_body(V* __restrict__ S, int lds_, int 
 // otherwise d[m] = (B[k], B[M-1-k]) with B[k] = 0 for k >= N.
 // B[k] += gamma g(u[k]) (+ tau phi2[k] for the start-up step) for this thread's k < N, in
 // place in LDS; returns whether some sine argument lies beyond the fast reduction's range
-template <int MODE, int GK, class L_t>
+template <int MODE, int GK, int US, class L_t>
 __device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const double* __restrict__ urow,
                                               const double* __restrict__ prow, const StepScalars& sc, int n) {
   constexpr int E = L_t::E, T = L_t::T;
@@ -565,7 +565,7 @@ __device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const d
     for (int h = 0; h < 2; ++h) {
       if (2 * (t + T * m) + h >= n) continue;   // B[k] = 0 outside the line
       const int lane_off = 2 * t + h;
-      const double uv = (urow + 2 * T * m)[lane_off];
+      const double uv = (urow + ((2 * T * m) << US))[lane_off << US];
       double gv = 0.0;
       if constexpr (GK == 1) {
         // far arguments (and inf / NaN) contribute nothing here: the fast reduction is not
@@ -588,7 +588,7 @@ __device__ __forceinline__ bool add_pointwise(const L_t& L, double* buf, const d
   return far;
 }
 
-template <int MODE, class L_t>
+template <int MODE, int US, class L_t>
 __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const V* __restrict__ srow,
                                           const double* __restrict__ urow, const double* __restrict__ prow,
                                           double* __restrict__ xo, bool live, const StepScalars& sc,
@@ -639,10 +639,10 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
     // one loop per kind of g (the kind is uniform: no per-element branches)
     bool far = false;   // some sin argument beyond the fast reduction's range
     switch (sc.gkind) {
-      case 1: far = add_pointwise<MODE, 1>(L, buf, urow, prow, sc, n); break;
-      case 2: add_pointwise<MODE, 2>(L, buf, urow, prow, sc, n); break;
-      case 3: add_pointwise<MODE, 3>(L, buf, urow, prow, sc, n); break;
-      default: add_pointwise<MODE, 0>(L, buf, urow, prow, sc, n); break;
+      case 1: far = add_pointwise<MODE, 1, US>(L, buf, urow, prow, sc, n); break;
+      case 2: add_pointwise<MODE, 2, US>(L, buf, urow, prow, sc, n); break;
+      case 3: add_pointwise<MODE, 3, US>(L, buf, urow, prow, sc, n); break;
+      default: add_pointwise<MODE, 0, US>(L, buf, urow, prow, sc, n); break;
     }
     if (sc.gkind == 1 && far) {
       // rare: the library sine for the far arguments of this lane (their fast-sine term
@@ -651,7 +651,7 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
       for (int i = 0; i < E; ++i) {
         const int m = i >> 1, h = i & 1;
         if (2 * (t + T * m) + h >= n) continue;
-        const double uv = (urow + 2 * T * m)[2 * t + h];
+        const double uv = (urow + ((2 * T * m) << US))[(2 * t + h) << US];
         if (!(fabs(uv) <= kSinFastMax)) {
           const int k = 2 * (t + T * m) + h;
           L.put_real(buf, k, L.get_real(buf, k) - sc.gamma * sin(uv));
@@ -668,7 +668,7 @@ __device__ __forceinline__ bool rhs_phase(const L_t& L, V* d, void* smem, const 
 }
 
 // rowblk: this workgroup's block of RowCfg<M>::LPW rows; smem: RowCfg<M>::LDS_BYTES bytes.
-template <int M, int MODE, int XS>
+template <int M, int MODE, int XS, int US = 0>
 __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M, int rowblk,
@@ -684,7 +684,8 @@ __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int ld
   constexpr int RMODE = MODE >= 3 ? MODE - 3 : MODE;
   static_assert(RMODE != 2 || XS == 0, "L_h output rows are plain");
   V d[E];
-  if (!rhs_phase<RMODE>(L, d, smem, S + pair_row(yy, lds_), u + (size_t)yy * ldu,
+  static_assert(US == 0 || RMODE == 0, "paired state rows only in run steps");
+  if (!rhs_phase<RMODE, US>(L, d, smem, S + pair_row(yy, lds_), u + (US ? pair_row(yy, ldu) : (size_t)yy * ldu),
                         RMODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, X + (size_t)yy * ldx, live, sc, tab,
                         root2M, n))
     return;
@@ -701,7 +702,7 @@ __device__ __forceinline__ void rows_rhs_gs_body(const V* __restrict__ S, int ld
 }
 
 // Mixed precision variant (MODE 0 / 1): FP32 solves, optional FP64 residual correction
-template <int M, int MODE>
+template <int M, int MODE, int US>
 __global__ void __launch_bounds__(MixRowCfg<M>::NT) SADI_OCC2
 rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                       const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
@@ -718,7 +719,7 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   const int yy = live ? y : 0;
   double* xo = X + (size_t)yy * ldx;
   V d[E];
-  rhs_phase<MODE>(L, d, smem, S + pair_row(yy, lds_), u + (size_t)yy * ldu,
+  rhs_phase<MODE, US>(L, d, smem, S + pair_row(yy, lds_), u + (US ? pair_row(yy, ldu) : (size_t)yy * ldu),
                   MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n);
   mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   if (live) {
@@ -817,7 +818,7 @@ __device__ __forceinline__ void cols_gs_body(double* X, int ldx, const double* u
 // in the transposed layout (its row cc is column cc here, contiguous); the new column is
 // stored as row cc of prev_t.  With `fwd` it is then transformed along its length (the next
 // step's row transform): its half spectrum goes to row cc of S.
-template <class L_t>
+template <int US, class L_t>
 __device__ __forceinline__ void update_transposed_and_forward(const L_t& L, V* d, unsigned char* smem,
                                                               const double* __restrict__ ucur,
                                                               double* __restrict__ prev_t, int n, int cc, bool live,
@@ -832,17 +833,20 @@ __device__ __forceinline__ void update_transposed_and_forward(const L_t& L, V* d
   // k = t + T m; rows k >= N are outside the grid (clamped loads, zero values).  Each new
   // value goes straight to memory and, for the transform, to LDS (the solve has finished
   // its LDS reads).
-  const double* uc = ucur + cc;
-  double* up = prev_t + (size_t)cc * n;
+  // US: both state arrays in paired rows (pitch N): element (y, x) at pair_row(y, N) + 2 x;
+  // T m is even, so slot m's rows start at the uniform offset T m N in either layout
+  const double* uc = ucur + (cc << US);
+  double* up = prev_t + (US ? pair_row(cc, n) : (size_t)cc * n);
   double* buf = reinterpret_cast<double*>(smem);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = tt + T * m, kc = min(k, n - 1);
     // uniform base of slot m plus a 32-bit lane offset (negative only for clamped rows)
-    const double a = (uc + (size_t)T * m * n)[(kc - T * m) * n];
-    const double b = (up + T * m)[kc - T * m];
+    const int ro = kc - T * m;
+    const double a = (uc + (size_t)T * m * n)[US ? (ro >> 1) * 2 * n + (kc & 1) : ro * n];
+    const double b = (up + ((T * m) << US))[US ? 2 * ro : ro];   // ro < 0 for clamped rows
     const double v = k < n ? 2.0 * a - b + d[m].x : 0.0;
-    if (live && k < n) (up + T * m)[tt] = v;
+    if (live && k < n) (up + ((T * m) << US))[tt << US] = v;
     if (fwd) L.put_real(buf, k, v);
   }
   if (!fwd) return;   // uniform
@@ -862,7 +866,7 @@ __device__ __forceinline__ void update_transposed_and_forward(const L_t& L, V* d
 }
 
 // grp: this workgroup's group of ColGSCfg<M>::LPW columns; smem: ColGSCfg<M>::LDS_BYTES bytes.
-template <int M, int XS>
+template <int M, int XS, int US = 0>
 __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
                                                  double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_,
                                                  FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M,
@@ -877,13 +881,13 @@ __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, i
   V d[E];
   load_column_pair<M, E, T, XS>(L, d, X, cc, ldx, smem, n);
   gs_solve(L, d, smem, tab, gs, n);
-  update_transposed_and_forward(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
+  update_transposed_and_forward<US>(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
 }
 
 // Mixed-precision form of cols_gs_fwd: the y-line solve of column cc of X (plain rows) in
 // float32 with one float64 residual correction (or none), then the same update and next
 // row transform.
-template <int M>
+template <int M, int US>
 __global__ void __launch_bounds__(MixColCfg<M>::NT) SADI_OCC2
 cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
                          double* __restrict__ prev_t, int n, V* __restrict__ S, int lds_, FFTTables<double> tab,
@@ -902,7 +906,7 @@ cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __
   V d[E];
   load_column_pair<M, E, T, 0>(L, d, X, cc, ldx, smem, n);
   mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
-  update_transposed_and_forward(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
+  update_transposed_and_forward<US>(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
 }
 
 // ----------------------------------------------------------------------------------
@@ -975,6 +979,46 @@ __global__ void __launch_bounds__(256) identity_kernel(double* A, int n) {
 }
 __global__ void __launch_bounds__(256) swap_transposed_kernel(double* cur, double* prev, int n) {
   swap_transposed_tiles(cur, prev, n);
+}
+
+// Plain N x N grid u (pitch N) <-> paired rows p (pitch N, N + 1 rows of room): element (y, x)
+// of p at pair_row(y, N) + 2 x.  trans: p holds the transpose of u.  32 x 32 tiles through
+// LDS, so that both sides are read and written along rows (for p, along both rows of a pair).
+template <bool TO_P>
+__global__ void __launch_bounds__(256) paired_state_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                           int n, int trans) {
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int y0 = blockIdx.y * 32, x0 = blockIdx.x * 32;
+  // read: element (y0 + r, x0 + tx) of the source grid in its own layout
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = ty + 8 * j, y = y0 + r, x = x0 + tx;
+    if (y < n && x < n) tile[r][tx] = TO_P ? src[(size_t)y * n + x] : src[pair_row(y, n) + 2 * (size_t)x];
+  }
+  __syncthreads();
+  // write: without trans the same element; with trans element (x0 + r, y0 + c) takes (c, r)
+  // of the tile.  For p the lanes run over (row parity, column) so that each wave writes the
+  // two rows of a pair together.
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int r, c;
+    if (TO_P) {               // lanes: c = (lane / 2), parity = lane % 2
+      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;   // 4 waves
+      const int q = w + 4 * j;                                     // pair index in the tile, 0..15
+      r = 2 * q + (lane & 1);
+      c = lane >> 1;
+    } else {
+      r = ty + 8 * j;
+      c = tx;
+    }
+    const int yd = (trans ? x0 : y0) + r, xd = (trans ? y0 : x0) + c;   // destination (row, column)
+    if (yd < n && xd < n) {
+      const double v = trans ? tile[c][r] : tile[r][c];
+      if (TO_P) dst[pair_row(yd, n) + 2 * (size_t)xd] = v;
+      else dst[(size_t)yd * n + xd] = v;
+    }
+  }
 }
 // batched (instance blockIdx.z): u[which] <- u[which]^T; (u[1], u[0]) <- (u[0]^T, u[1])
 __global__ void __launch_bounds__(256) transpose_inplace_batched(const BatchInst* __restrict__ bi, int which, int n) {
@@ -1078,13 +1122,13 @@ __device__ __forceinline__ int rhs_row_block() {
   return RowCfg<M>::LPW == 1 ? paired_row_block() : (int)blockIdx.x;
 }
 
-template <int M, int MODE, int XS>
+template <int M, int MODE, int XS, int US>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
 rows_rhs_gs_kernel(const V* __restrict__ S, int lds_, const double* __restrict__ u, int ldu,
                    const double* __restrict__ phi2, double* __restrict__ X, int ldx, int n,
                    StepScalars sc, FFTTables<double> tab, GSTables64 gs, const V* __restrict__ root2M) {
   __shared__ __align__(16) unsigned char smem[RowCfg<M>::LDS_BYTES];
-  rows_rhs_gs_body<M, MODE, XS>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M, rhs_row_block<M>(), smem);
+  rows_rhs_gs_body<M, MODE, XS, US>(S, lds_, u, ldu, phi2, X, ldx, n, sc, tab, gs, root2M, rhs_row_block<M>(), smem);
 }
 template <int M, int MODE>
 __global__ void __launch_bounds__(RowCfg<M>::NT) SADI_OCC4
@@ -1110,7 +1154,7 @@ cols_gs_batched(const BatchInst* __restrict__ bi, int ldx, int n, FFTTables<doub
   cols_gs_body<M, 2, 0>(p.X, ldx, nullptr, nullptr, nullptr, n, n, tab, gs, ngroups);
 }
 
-template <int M>
+template <int M, int US>
 __global__ void __launch_bounds__(ColGSCfg<M>::NT) SADI_OCC4
 cols_gs_fwd_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur, double* __restrict__ prev_t,
                    int n, V* __restrict__ S, int lds_, FFTTables<double> tab, GSTables64 gs,
@@ -1118,7 +1162,7 @@ cols_gs_fwd_kernel(const double* __restrict__ X, int ldx, const double* __restri
   __shared__ __align__(16) unsigned char smem[ColGSCfg<M>::LDS_BYTES];
   const int grp = xcd_group(ngroups);
   if (grp >= ngroups) return;   // whole workgroup
-  cols_gs_fwd_body<M, 1>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, grp, fwd, smem);
+  cols_gs_fwd_body<M, 1, US>(X, ldx, ucur, prev_t, n, S, lds_, tab, gs, root2M, grp, fwd, smem);
 }
 // batched: instance blockIdx.y; u[ic] = u^n in this step's layout, u[ip] = u^{n-1} transposed
 template <int M>
@@ -1484,24 +1528,27 @@ int rhs_grid(int n) {
 template <int M>
 void launch_rows_rhs_gs(int mode, const V* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
                         int ldx, bool x_paired, int n, const StepScalars& sc, const FFTTables<double>& tab,
-                        const GSTables64& gs, const V* root2M, hipStream_t st) {
+                        const GSTables64& gs, const V* root2M, hipStream_t st, bool u_paired) {
   const int grid = rhs_grid<M>(n);
   const dim3 blk(RowCfg<M>::NT);
-  // mode 2 (L_h only) writes plain rows
-  if (mode == 0 && x_paired)
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 1>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+  // mode 2 (L_h only) writes plain rows; the state in paired rows only in run steps (mode 0)
+  if (mode == 0 && x_paired && u_paired)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 1, 1>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n,
+                       sc, tab, gs, root2M);
+  else if (mode == 0 && x_paired)
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 1, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
                        tab, gs, root2M);
   else if (mode == 0)
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 0, 0, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
                        tab, gs, root2M);
   else if (mode == 1 && x_paired)
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1, 1>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1, 1, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
                        tab, gs, root2M);
   else if (mode == 1)
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 1, 0, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
                        tab, gs, root2M);
   else
-    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 2, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
+    hipLaunchKernelGGL((rows_rhs_gs_kernel<M, 2, 0, 0>), dim3(grid), blk, 0, st, S, lds_, u, ldu, phi2, X, ldx, n, sc,
                        tab, gs, root2M);
 }
 
@@ -1534,13 +1581,16 @@ void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, cons
 template <int M>
 void launch_rows_rhs_mixed(int mode, const V* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
                            int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const MixedTables& mx,
-                           const V* root2M, hipStream_t st) {
+                           const V* root2M, hipStream_t st, bool u_paired) {
   const int grid = (n + MixRowCfg<M>::LPW - 1) / MixRowCfg<M>::LPW;
-  if (mode == 0)
-    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+  if (mode == 0 && u_paired)
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0, 1>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+                       phi2, X, ldx, n, sc, tab, mx, root2M);
+  else if (mode == 0)
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0, 0>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
                        phi2, X, ldx, n, sc, tab, mx, root2M);
   else
-    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 1>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 1, 0>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
                        phi2, X, ldx, n, sc, tab, mx, root2M);
 }
 
@@ -1554,11 +1604,16 @@ void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTab
 
 template <int M>
 void launch_cols_gs_fwd(const double* X, int ldx, const double* ucur, double* prev_t, int n, V* S, int lds_, bool fwd,
-                        const FFTTables<double>& tab, const GSTables64& gs, const V* root2M, hipStream_t st) {
+                        const FFTTables<double>& tab, const GSTables64& gs, const V* root2M, hipStream_t st,
+                        bool u_paired) {
   const int ngroups = (n + ColGSCfg<M>::LPW - 1) / ColGSCfg<M>::LPW;
   const int grid = ((ngroups + 7) / 8) * 8;
-  hipLaunchKernelGGL(cols_gs_fwd_kernel<M>, dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n, S,
-                     lds_, tab, gs, root2M, ngroups, fwd ? 1 : 0);
+  if (u_paired)
+    hipLaunchKernelGGL((cols_gs_fwd_kernel<M, 1>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n,
+                       S, lds_, tab, gs, root2M, ngroups, fwd ? 1 : 0);
+  else
+    hipLaunchKernelGGL((cols_gs_fwd_kernel<M, 0>), dim3(grid), dim3(ColGSCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n,
+                       S, lds_, tab, gs, root2M, ngroups, fwd ? 1 : 0);
 }
 
 void launch_identity(double* A, int n, hipStream_t st) {
@@ -1573,6 +1628,16 @@ void launch_transpose_inplace(double* A, int n, hipStream_t st) {
   hipLaunchKernelGGL(transpose_inplace_kernel, dim3(nt, nt), dim3(256), 0, st, A, n);
 }
 
+void launch_state_to_paired(const double* u, double* p, int n, bool trans, hipStream_t st) {
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(paired_state_kernel<true>, dim3(nt, nt), dim3(256), 0, st, u, p, n, trans ? 1 : 0);
+}
+
+void launch_state_from_paired(const double* p, double* u, int n, bool trans, hipStream_t st) {
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(paired_state_kernel<false>, dim3(nt, nt), dim3(256), 0, st, p, u, n, trans ? 1 : 0);
+}
+
 void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st) {
   const int nt = (n + 31) / 32;
   hipLaunchKernelGGL(swap_transposed_kernel, dim3(nt, nt), dim3(256), 0, st, cur, prev, n);
@@ -1581,11 +1646,15 @@ void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st) {
 template <int M>
 void launch_cols_gs_fwd_mixed(const double* X, int ldx, const double* ucur, double* prev_t, int n, V* S, int lds_,
                               bool fwd, const FFTTables<double>& tab, const MixedTables& mx, const V* root2M,
-                              hipStream_t st) {
+                              hipStream_t st, bool u_paired) {
   const int ngroups = (n + MixColCfg<M>::LPW - 1) / MixColCfg<M>::LPW;
   const int grid = ((ngroups + 7) / 8) * 8;
-  hipLaunchKernelGGL(cols_gs_fwd_mixed_kernel<M>, dim3(grid), dim3(MixColCfg<M>::NT), 0, st, X, ldx, ucur, prev_t, n,
-                     S, lds_, tab, mx, root2M, ngroups, fwd ? 1 : 0);
+  if (u_paired)
+    hipLaunchKernelGGL((cols_gs_fwd_mixed_kernel<M, 1>), dim3(grid), dim3(MixColCfg<M>::NT), 0, st, X, ldx, ucur,
+                       prev_t, n, S, lds_, tab, mx, root2M, ngroups, fwd ? 1 : 0);
+  else
+    hipLaunchKernelGGL((cols_gs_fwd_mixed_kernel<M, 0>), dim3(grid), dim3(MixColCfg<M>::NT), 0, st, X, ldx, ucur,
+                       prev_t, n, S, lds_, tab, mx, root2M, ngroups, fwd ? 1 : 0);
 }
 
 template <int M>
@@ -1674,22 +1743,23 @@ void launch_batch_leapfrog(int mode, const BatchInst* bi, int count, int ic, int
                                     hipStream_t);                                                                \
   template void launch_rows_rhs_gs<M>(int, const V*, int, const double*, int, const double*, double*, int, bool, \
                                       int, const StepScalars&, const FFTTables<double>&, const GSTables64&,       \
-                                      const V*, hipStream_t);                                                    \
+                                      const V*, hipStream_t, bool);                                              \
   template void launch_rows_gs<M>(double*, int, int, int, const FFTTables<double>&, const GSTables64&,            \
                                   hipStream_t);                                                                  \
   template void launch_cols_gs<M>(int, const double*, int, const double*, const double*, double*, int, int,       \
                                   const FFTTables<double>&, const GSTables64&, hipStream_t);                     \
   template void launch_cols_gs_fwd<M>(const double*, int, const double*, double*, int, V*, int, bool,            \
-                                      const FFTTables<double>&, const GSTables64&, const V*, hipStream_t);       \
+                                      const FFTTables<double>&, const GSTables64&, const V*, hipStream_t, bool); \
   template void launch_rows_rhs_mixed<M>(int, const V*, int, const double*, int, const double*, double*, int,     \
                                          int, const StepScalars&, const FFTTables<double>&, const MixedTables&,  \
-                                         const V*, hipStream_t);                                                 \
+                                         const V*, hipStream_t, bool);                                           \
   template void launch_rows_gs_mixed<M>(double*, int, int, int, const FFTTables<double>&, const MixedTables&,     \
                                         hipStream_t);                                                            \
   template void launch_cols_gs_mixed<M>(int, const double*, int, const double*, const double*, double*, int, int, \
                                         const FFTTables<double>&, const MixedTables&, hipStream_t);                \
   template void launch_cols_gs_fwd_mixed<M>(const double*, int, const double*, double*, int, V*, int, bool,      \
-                                            const FFTTables<double>&, const MixedTables&, const V*, hipStream_t); \
+                                            const FFTTables<double>&, const MixedTables&, const V*, hipStream_t,  \
+                                            bool);                                                               \
   template void launch_batch_rows_fwd<M>(int, const BatchInst*, int, int, int, int, int, int,                     \
                                          const FFTTables<double>&, hipStream_t);                                  \
   template void launch_batch_cols_conv<M>(const BatchInst*, int, int, int, int, const FFTTables<double>&,         \

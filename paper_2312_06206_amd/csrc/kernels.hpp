@@ -242,7 +242,7 @@ void launch_cols_conv(double2* S, int lds_, int n, const double* lam, int ldlam,
 template <int M>
 void launch_rows_rhs_gs(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2, double* X,
                         int ldx, bool x_paired, int n, const StepScalars& sc, const FFTTables<double>& tab,
-                        const GSTables64& gs, const double2* root2M, hipStream_t st);
+                        const GSTables64& gs, const double2* root2M, hipStream_t st, bool u_paired = false);
 template <int M>
 void launch_rows_gs(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab, const GSTables64& gs,
                     hipStream_t st);
@@ -250,13 +250,17 @@ template <int M>
 void launch_cols_gs(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                     int ldu, int n, const FFTTables<double>& tab, const GSTables64& gs, hipStream_t st);
 // y-line solves of X (paired rows), the update into prev_t's rows (transposed layout) and,
-// with fwd, the next step's row transform of the new state into S
+// with fwd, the next step's row transform of the new state into S.  u_paired: both state
+// arrays in paired rows (launch_state_to_paired) instead of plain rows.
 template <int M>
 void launch_cols_gs_fwd(const double* X, int ldx, const double* ucur, double* prev_t, int n, double2* S, int lds_,
                         bool fwd, const FFTTables<double>& tab, const GSTables64& gs, const double2* root2M,
-                        hipStream_t st);
+                        hipStream_t st, bool u_paired = false);
 // N x N: A <- A^T; (cur, prev) <- (prev^T, cur); A <- I (dense row-major, pitch N)
 void launch_transpose_inplace(double* A, int n, hipStream_t st);
+// plain grid (pitch N) <-> paired rows (pitch N, room for N + 1 rows), optionally transposed
+void launch_state_to_paired(const double* u, double* p, int n, bool trans, hipStream_t st);
+void launch_state_from_paired(const double* p, double* u, int n, bool trans, hipStream_t st);
 void launch_identity(double* A, int n, hipStream_t st);
 void launch_swap_transposed(double* cur, double* prev, int n, hipStream_t st);
 // batched forms (instances in blockIdx.y; iu / ip select u[0] or u[1]).  Row pass modes:
@@ -304,7 +308,7 @@ void launch_adjoint_finish(const double* partial, int nrows, double c2, double k
 template <int M>
 void launch_rows_rhs_mixed(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2,
                            double* X, int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab,
-                           const MixedTables& mx, const double2* root2M, hipStream_t st);
+                           const MixedTables& mx, const double2* root2M, hipStream_t st, bool u_paired = false);
 template <int M>
 void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTables<double>& tab,
                           const MixedTables& mx, hipStream_t st);
@@ -316,6 +320,6 @@ void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur
 template <int M>
 void launch_cols_gs_fwd_mixed(const double* X, int ldx, const double* ucur, double* prev_t, int n, double2* S,
                               int lds_, bool fwd, const FFTTables<double>& tab, const MixedTables& mx,
-                              const double2* root2M, hipStream_t st);
+                              const double2* root2M, hipStream_t st, bool u_paired = false);
 
 }  // namespace sadi

@@ -21,6 +21,7 @@ namespace sadi_impl {
 
 thread_local std::string g_last_error;
 thread_local int g_setup_threads = 0;
+thread_local bool g_setup_no_run_state = false;
 
 sadi_status fail(sadi_status st, const std::string& msg) {
   g_last_error = msg;
@@ -139,9 +140,9 @@ template <int M> struct ColsConv {
 };
 template <int M> struct RowsRhs {
   static void run(const sadi_ctx* c, int mode, const double* u, const double* phi2, double* X, int ldx,
-                  const sadi::StepScalars& sc) {
+                  const sadi::StepScalars& sc, bool u_paired = false) {
     sadi::launch_rows_rhs_gs<M>(mode, c->S, c->ldS, u, c->n, phi2, X, ldx, c->x_paired, c->n, sc, tables(c),
-                                step_gs_tables(c), c->root2M, c->stream);
+                                step_gs_tables(c), c->root2M, c->stream, u_paired);
   }
 };
 template <int M> struct ColsGS {
@@ -151,9 +152,9 @@ template <int M> struct ColsGS {
   }
 };
 template <int M> struct ColsGSFwd {   // y-sweep, update into the transposed layout, next row pass
-  static void run(const sadi_ctx* c, const double* ucur, double* prev_t, bool fwd) {
+  static void run(const sadi_ctx* c, const double* ucur, double* prev_t, bool fwd, bool u_paired) {
     sadi::launch_cols_gs_fwd<M>(c->X, c->ldX, ucur, prev_t, c->n, c->S, c->ldS, fwd, tables(c), step_gs_tables(c),
-                                c->root2M, c->stream);
+                                c->root2M, c->stream, u_paired);
   }
 };
 template <int M> struct ColsGSPitched {   // in-place y-line solves of an N x ldX buffer
@@ -189,9 +190,10 @@ sadi::MixedTables mixed_tables(const sadi_ctx* c) {
   return mx;
 }
 template <int M> struct RowsRhsMixed {
-  static void run(const sadi_ctx* c, int mode, const double* u, const double* phi2, const sadi::StepScalars& sc) {
+  static void run(const sadi_ctx* c, int mode, const double* u, const double* phi2, const sadi::StepScalars& sc,
+                  bool u_paired = false) {
     sadi::launch_rows_rhs_mixed<M>(mode, c->S, c->ldS, u, c->n, phi2, c->X, c->ldX, c->n, sc, tables(c),
-                                   mixed_tables(c), c->root2M, c->stream);
+                                   mixed_tables(c), c->root2M, c->stream, u_paired);
   }
 };
 template <int M> struct ColsGSMixed {
@@ -201,9 +203,9 @@ template <int M> struct ColsGSMixed {
   }
 };
 template <int M> struct ColsGSFwdMixed {   // mixed y-sweep, update into the transposed layout, next row pass
-  static void run(const sadi_ctx* c, const double* ucur, double* prev_t, bool fwd) {
+  static void run(const sadi_ctx* c, const double* ucur, double* prev_t, bool fwd, bool u_paired) {
     sadi::launch_cols_gs_fwd_mixed<M>(c->X, c->ldX, ucur, prev_t, c->n, c->S, c->ldS, fwd, tables(c), mixed_tables(c),
-                                      c->root2M, c->stream);
+                                      c->root2M, c->stream, u_paired);
   }
 };
 template <int M> struct RowsGSMixed {
@@ -412,6 +414,10 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   const size_t o_S = place(std::max(sizeof(double2) * srows * c->ldS, fbytes));
   const size_t o_X = place(sizeof(double) * xrows * c->ldX);
   const size_t o_lam = place(sizeof(double) * lam_elems);
+  // sadi_run's paired-row copies of the state (three-kernel runs; not for batch members)
+  const bool run_state = !c->tail_gemm && !g_setup_no_run_state;
+  const size_t run_bytes = run_state ? sizeof(double) * (size_t)(n + 1) * n : 0;
+  const size_t o_run0 = run_state ? place(run_bytes) : 0, o_run1 = run_state ? place(run_bytes) : 0;
   const size_t o_fw = o_S, o_fa = o_fw + sizeof(double) * (ls ? ls->nq : 0), o_fc = o_fa + sizeof(double) * ft;
   // the first column of H_M (double-double) for the device Levinson recursion and its
   // result c, in the adjoint's partial-sum space (4 N doubles, unused until a step), which
@@ -436,6 +442,10 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
   c->sig_e = (double*)(pool + o_sige);
   c->sig_o = (double*)(pool + o_sigo);
   c->partial = (double*)(pool + o_partial);
+  if (run_state) {
+    c->run_state[0] = (double*)(pool + o_run0);
+    c->run_state[1] = (double*)(pool + o_run1);
+  }
   c->S = (double2*)(pool + o_S);
   c->X = (double*)(pool + o_X);
   c->lam2d = (double*)(pool + o_lam);
@@ -660,24 +670,34 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
       if (e) (void)hipEventRecord(e, c->stream);
     };
     const sadi::StepScalars sc = scalars(c, false);
-    sadi::launch_transpose_inplace(u_prev, c->n, c->stream);
+    // the state in paired rows for the run (the y-sweep then reads u^n by row pairs, as it
+    // reads X), in the context's copies, when the context has them
+    const bool paired = c->run_state[0] != nullptr;
     double* a = u_prev;   // u^{n-1}, transposed relative to b
     double* b = u_cur;    // u^n in this step's layout
+    if (paired) {
+      sadi::launch_state_to_paired(u_prev, c->run_state[0], c->n, true, c->stream);
+      sadi::launch_state_to_paired(u_cur, c->run_state[1], c->n, false, c->stream);
+      a = c->run_state[0];
+      b = c->run_state[1];
+    } else {
+      sadi::launch_transpose_inplace(u_prev, c->n, c->stream);
+    }
     for (int s = 0; s < nsteps; ++s) {
       mark(0);
-      if (s == 0) dispatch_m<RowsFwd>(c->m, c, b, nullptr);
+      if (s == 0) dispatch_m<RowsFwd>(c->m, c, u_cur, nullptr);   // u^n in plain rows
       mark(1);
       dispatch_m<ColsConv>(c->m, c);
       mark(2);
       if (c->prec == SADI_FP64)
-        dispatch_m<RowsRhs>(c->m, c, 0, b, nullptr, c->X, c->ldX, sc);
+        dispatch_m<RowsRhs>(c->m, c, 0, b, nullptr, c->X, c->ldX, sc, paired);
       else
-        dispatch_m<RowsRhsMixed>(c->m, c, 0, b, nullptr, sc);
+        dispatch_m<RowsRhsMixed>(c->m, c, 0, b, nullptr, sc, paired);
       mark(3);
       if (c->prec == SADI_FP64)
-        dispatch_m<ColsGSFwd>(c->m, c, b, a, s + 1 < nsteps);
+        dispatch_m<ColsGSFwd>(c->m, c, b, a, s + 1 < nsteps, paired);
       else
-        dispatch_m<ColsGSFwdMixed>(c->m, c, b, a, s + 1 < nsteps);
+        dispatch_m<ColsGSFwdMixed>(c->m, c, b, a, s + 1 < nsteps, paired);
       mark(4);
       if (c->timing && c->timed_steps < sadi_ctx::kMaxTimedSteps) ++c->timed_steps;
       sadi_status st = check_launch();
@@ -685,10 +705,14 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
       std::swap(a, b);
     }
     // b holds the newest state (transposed when nsteps is odd), a the one before
-    if (nsteps % 2 == 0)
+    if (paired) {
+      sadi::launch_state_from_paired(b, u_cur, c->n, nsteps % 2 == 1, c->stream);
+      sadi::launch_state_from_paired(a, u_prev, c->n, nsteps % 2 == 0, c->stream);
+    } else if (nsteps % 2 == 0) {
       sadi::launch_transpose_inplace(a, c->n, c->stream);
-    else
+    } else {
       sadi::launch_swap_transposed(u_cur, u_prev, c->n, c->stream);
+    }
     return check_launch();
   }
   // corrections of rank above 3 (float64 only): four kernels per step in the natural layout,
