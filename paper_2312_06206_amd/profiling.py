@@ -70,9 +70,9 @@ def find_csv(directory: str, suffix: str = "counter_collection.csv") -> str:
 
 
 # the kernels of a step n >= 1 inside a multi-step run, by name prefix and template tail
-# kernels of a run of steps (the row transform runs once per run)
+# kernels of a run of steps (the row transform runs once per run; the state in paired rows)
 KERNEL_KEYS = {"rows_fwd": ("rows_fwd_kernel<", ", 0, 0>"), "cols_conv": ("cols_conv_kernel<", ">"),
-               "rows_rhs_gs": ("rows_rhs_gs_kernel<", ", 0, 1>"), "cols_gs_fwd": ("cols_gs_fwd_kernel<", ">")}
+               "rows_rhs_gs": ("rows_rhs_gs_kernel<", ", 0, 1, 1>"), "cols_gs_fwd": ("cols_gs_fwd_kernel<", ", 1>")}
 
 
 def kernel_key(name: str, m: int):

@@ -12,12 +12,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_kernel_keys_match_the_step_kernels():
     m = 4096
     names = {
-        "void sadi::cols_gs_fwd_kernel<4096>(double const*, int, ...)": "cols_gs_fwd",
+        "void sadi::cols_gs_fwd_kernel<4096, 1>(double const*, int, ...)": "cols_gs_fwd",
         "void sadi::cols_conv_kernel<4096>(HIP_vector_type<double, 2u>*, int, ...)": "cols_conv",
-        "void sadi::rows_rhs_gs_kernel<4096, 0, 1>(HIP_vector_type<double, 2u> const*, ...)": "rows_rhs_gs",
+        "void sadi::rows_rhs_gs_kernel<4096, 0, 1, 1>(HIP_vector_type<double, 2u> const*, ...)": "rows_rhs_gs",
         "void sadi::rows_fwd_kernel<4096, 0, 0>(double const*, double*, ...)": "rows_fwd",
         # not step kernels of a run
-        "void sadi::rows_rhs_gs_kernel<4096, 1, 1>(...)": None,
+        "void sadi::rows_rhs_gs_kernel<4096, 1, 1, 0>(...)": None,
+        "void sadi::rows_rhs_gs_kernel<4096, 0, 1, 0>(...)": None,
+        "void sadi::cols_gs_fwd_kernel<4096, 0>(...)": None,
         "void sadi::cols_gs_kernel<4096, 2, 0>(...)": None,
         "void sadi::cols_conv_kernel<1024>(...)": None,
         "void sadi::cols_conv_batched<4096>(...)": None,
