@@ -213,10 +213,12 @@ def test_long_run_n1023():
         assert rel(got_prev, ref_prev) < 1e-10, prec
 
 
-@pytest.mark.parametrize("n,nsteps", [(127, 0), (127, 1), (127, 2), (127, 6), (127, 7), (31, 3), (1023, 4)])
+@pytest.mark.parametrize("n,nsteps", [(127, 0), (127, 1), (127, 2), (127, 6), (127, 7), (31, 3), (1023, 4),
+                                       (30, 3), (30, 4), (126, 5)])
 def test_run_even_and_odd_counts(n, nsteps):
-    """Runs of zero, one and several steps (the update of each step is deferred into the
-    next step's row transform; an odd count exchanges the two arrays at the end)."""
+    """Runs of zero, one and several steps: the state is copied into paired rows (u_prev
+    transposed) and back, the grid orientation alternating from step to step; odd and even
+    N (N = 30, 126: the last row pair full; M - N = 2 corrected inside the line solves)."""
     alpha, tau = 1.6, 2e-3
     _say(f"run parity n={n} steps={nsteps}")
     P = oracle_problem(alpha, n, tau)
