@@ -254,8 +254,9 @@ typedef enum { SADI_PATH_FFT_GS = 0, SADI_PATH_DENSE = 1, SADI_PATH_DENSE_MIXED 
  * may take the two dense paths; their explicit inverses (N*N doubles per instance) and,
  * for SADI_PATH_DENSE_MIXED, the FP32 copies and H itself (N*N floats and doubles) are
  * built when a dense path is first timed (sadi_batch_tune) or chosen (sadi_batch_set_path).
- * Host-synchronous; allocates everything the batch needs.  All groups start on
- * SADI_PATH_FFT_GS. */
+ * Host-synchronous; allocates everything the batch needs.  The instances are set up on
+ * concurrent host threads; the line tables of all of them (N + 1 a power of two) are then
+ * built in one pair of launches.  All groups start on SADI_PATH_FFT_GS. */
 sadi_status sadi_batch_create(int count, const int* n, const double* alpha, const double* kappa, double tau,
                               const double* domain, int dense_max_n, sadi_batch** out);
 

@@ -537,6 +537,7 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
         (void)hipSetDevice(device);   // the caller's device, as for sadi_setup
         g_setup_threads = inner;
         g_setup_no_run_state = true;   // batch members take batched steps only
+        g_setup_defer_gs = true;       // their line tables: one launch for all, below
         for (int i = w; i < count; i += workers) {
           status[i] = sadi_setup(alpha[i], kappa[i], n[i], tau, domain, &b->ctx[i]);
           if (status[i] != SADI_OK) errors[i] = sadi_last_error();
@@ -556,6 +557,30 @@ sadi_status sadi_batch_create(int count, const int* n, const double* alpha, cons
   }
   b->stream = b->own_stream;
   for (sadi_ctx* c : b->ctx) c->stream = b->stream;
+  {
+    // the members' line tables (Levinson recursion and tables, one workgroup per member)
+    std::vector<sadi::GsJob> jobs;
+    int max_m = 0;
+    for (sadi_ctx* c : b->ctx)
+      if (c->gs_pending) {
+        jobs.push_back(c->gs_job);
+        max_m = std::max(max_m, c->gs_job.m);
+      }
+    if (!jobs.empty()) {
+      void* dj = nullptr;
+      if (hipMalloc(&dj, sizeof(sadi::GsJob) * jobs.size()) != hipSuccess)
+        return bail(fail(SADI_E_NOMEM, "line table jobs"));
+      hipError_t e = hipMemcpy(dj, jobs.data(), sizeof(sadi::GsJob) * jobs.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) {
+        sadi::launch_gs_generator_batched((const sadi::GsJob*)dj, (int)jobs.size(), max_m, b->stream);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+      (void)hipFree(dj);
+      if (e != hipSuccess) return bail(fail(SADI_E_DEVICE, std::string("line tables: ") + hipGetErrorString(e)));
+      for (sadi_ctx* c : b->ctx) c->gs_pending = false;
+    }
+  }
 
   std::map<int, int> by_n;
   for (int i = 0; i < count; ++i) {

@@ -22,6 +22,9 @@ bool supported_n(int n);
 extern thread_local int g_setup_threads;
 // set-up on this thread skips the run state buffers (contexts that only take batched steps)
 extern thread_local bool g_setup_no_run_state;
+// set-up on this thread leaves the device line tables (N + 1 = M) to the caller, who runs
+// them for many contexts in one launch (sadi_ctx::gs_pending)
+extern thread_local bool g_setup_defer_gs;
 // argument checks of sadi_setup (allow2: alpha = 2 accepted, for injected tables)
 sadi_status validate_problem(double alpha, double kappa, int n, double tau, const double* domain, bool allow2);
 }  // namespace sadi_impl
@@ -86,6 +89,10 @@ struct sadi_ctx {
   // sadi_run's copies of the two state arrays in paired rows (N + 1 rows of pitch N each),
   // or null (the run then works on the caller's arrays in plain rows)
   double* run_state[2] = {nullptr, nullptr};
+  // set up with the device line tables deferred: their job (the tables lam_s, lam_c, f and
+  // copies are not yet written while gs_pending)
+  bool gs_pending = false;
+  sadi::GsJob gs_job{};
   // device the context was set up on, and that device's static work space of
   // sadi_step_noalloc (null if its address could not be resolved)
   int device = 0;

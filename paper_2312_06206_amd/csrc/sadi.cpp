@@ -22,6 +22,7 @@ namespace sadi_impl {
 thread_local std::string g_last_error;
 thread_local int g_setup_threads = 0;
 thread_local bool g_setup_no_run_state = false;
+thread_local bool g_setup_defer_gs = false;
 
 sadi_status fail(sadi_status st, const std::string& msg) {
   g_last_error = msg;
@@ -493,7 +494,11 @@ sadi_status build_ctx(double alpha, double kappa, int n, double tau, const doubl
       }
     return bail(e);
   };
-  if (device_gs) {   // c = H_M^-1 e_1 (one workgroup, sequential in k), then the tables
+  if (device_gs && g_setup_defer_gs) {   // the caller runs the tables (with other contexts')
+    c->gs_job = sadi::GsJob{(const double*)(pool + o_thi), (const double*)(pool + o_tlo), (double*)(pool + o_cvec),
+                            c->root2M, c->lam_s, c->lam_c, c->f, c->lam_s32, c->lam_c32, c->f32, m};
+    c->gs_pending = true;
+  } else if (device_gs) {   // c = H_M^-1 e_1 (one workgroup, sequential in k), then the tables
     SADI_HIP_OR(take_setup_stream(sdev, &sgs), bail_s);
     sadi::launch_gs_generator((const double*)(pool + o_thi), (const double*)(pool + o_tlo), m,
                               (double*)(pool + o_cvec), c->root2M, c->lam_s, c->lam_c, c->f, c->lam_s32, c->lam_c32,

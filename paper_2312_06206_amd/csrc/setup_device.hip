@@ -164,8 +164,8 @@ __device__ DD block_sum_dd(DD v, DD* red) {
 // [f; 0] updated to ([f; 0] - e [0; J f]) / (1 - e^2), pairs (i, k - i) in place.  The
 // thread that forms the new f[i] also adds its terms of the next e, so each step needs one
 // barrier (the block sum's; its partials alternate between two buffers).  c = f rounded.
-__global__ void __launch_bounds__(kLevThreads)
-levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo, int m, double* __restrict__ c) {
+__device__ __forceinline__ void levinson_body(const double* __restrict__ t_hi, const double* __restrict__ t_lo, int m,
+                                              double* __restrict__ c) {
   __shared__ double fh[kLevMaxM], fl[kLevMaxM], th[kLevMaxM], tl[kLevMaxM];
   __shared__ DD red[2][kLevThreads / 64];
   for (int i = threadIdx.x; i < m; i += kLevThreads) {
@@ -205,17 +205,25 @@ levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo
   __syncthreads();
   for (int i = threadIdx.x; i < m; i += kLevThreads) c[i] = fh[i] + fl[i];
 }
+__global__ void __launch_bounds__(kLevThreads)
+levinson_kernel(const double* __restrict__ t_hi, const double* __restrict__ t_lo, int m, double* __restrict__ c) {
+  levinson_body(t_hi, t_lo, m, c);
+}
+// one workgroup per job
+__global__ void __launch_bounds__(kLevThreads) levinson_batched(const GsJob* __restrict__ jobs) {
+  const GsJob& j = jobs[blockIdx.x];
+  levinson_body(j.t_hi, j.t_lo, j.m, j.c);
+}
 
 // The tables of Algorithm 1 from c = H_M^-1 e_1 (p1 = c[0]), by direct DFTs summed in
 // double-double: lam_c[k] = fft(c)[k] / M and lam_s[k] = fft(Q s)[k] / (2 p1 M) with
 // s = (p1, -c[M-1], ..., -c[1]) and Q = diag(e^{-i pi j / M}); the correction f[k] =
 // c[M-1-k] / p1 (k < N = M - 1); and their float32 copies.  q[j] = e^{-i pi j / M}, j < M.
-__global__ void __launch_bounds__(256)
-gs_tables_kernel(const double* __restrict__ c, int m, const double2* __restrict__ q, double2* __restrict__ lam_s,
-                 double2* __restrict__ lam_c, double* __restrict__ f, float2* __restrict__ lam_s32,
-                 float2* __restrict__ lam_c32, float* __restrict__ f32) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= m) return;
+// Frequency k (< m) of those tables.
+__device__ __forceinline__ void gs_tables_body(const double* __restrict__ c, int m, const double2* __restrict__ q,
+                                               double2* __restrict__ lam_s, double2* __restrict__ lam_c,
+                                               double* __restrict__ f, float2* __restrict__ lam_s32,
+                                               float2* __restrict__ lam_c32, float* __restrict__ f32, int k) {
   const int two_m = 2 * m;
   // e^{-i pi idx / M} for 0 <= idx < 2M
   auto w = [&](int idx) -> double2 {
@@ -253,6 +261,21 @@ gs_tables_kernel(const double* __restrict__ c, int m, const double2* __restrict_
     f32[k] = (float)fk;
   }
 }
+__global__ void __launch_bounds__(256)
+gs_tables_kernel(const double* __restrict__ c, int m, const double2* __restrict__ q, double2* __restrict__ lam_s,
+                 double2* __restrict__ lam_c, double* __restrict__ f, float2* __restrict__ lam_s32,
+                 float2* __restrict__ lam_c32, float* __restrict__ f32) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= m) return;
+  gs_tables_body(c, m, q, lam_s, lam_c, f, lam_s32, lam_c32, f32, k);
+}
+// job blockIdx.y, frequencies blockIdx.x * 256 + threadIdx.x
+__global__ void __launch_bounds__(256) gs_tables_batched(const GsJob* __restrict__ jobs) {
+  const GsJob& j = jobs[blockIdx.y];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= j.m) return;
+  gs_tables_body(j.c, j.m, j.q, j.lam_s, j.lam_c, j.f, j.lam_s32, j.lam_c32, j.f32, k);
+}
 
 }  // namespace
 
@@ -261,6 +284,12 @@ void launch_gs_generator(const double* t_hi, const double* t_lo, int m, double* 
   hipLaunchKernelGGL(levinson_kernel, dim3(1), dim3(kLevThreads), 0, st, t_hi, t_lo, m, c);
   hipLaunchKernelGGL(gs_tables_kernel, dim3((m + 255) / 256), dim3(256), 0, st, c, m, q, lam_s, lam_c, f, lam_s32,
                      lam_c32, f32);
+}
+
+void launch_gs_generator_batched(const GsJob* jobs, int njobs, int max_m, hipStream_t st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(levinson_batched, dim3(njobs), dim3(kLevThreads), 0, st, jobs);
+  hipLaunchKernelGGL(gs_tables_batched, dim3((max_m + 255) / 256, njobs), dim3(256), 0, st, jobs);
 }
 
 // The node table of the current device (built on first use; host-synchronous then).
