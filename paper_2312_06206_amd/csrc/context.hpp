@@ -11,6 +11,7 @@
 
 #include "../../include/sadi.h"
 #include "kernels.hpp"
+#include "setup_device.hpp"
 
 namespace sadi_impl {
 // record msg as the calling thread's last error and return st

@@ -228,22 +228,6 @@ void launch_toeplitz_fill(const ToeplitzPtrs* batch, int count, int n, hipStream
 // c: m doubles of work space.
 void launch_gs_generator(const double* t_hi, const double* t_lo, int m, double* c, const double2* q, double2* lam_s,
                          double2* lam_c, double* f, float2* lam_s32, float2* lam_c32, float* f32, hipStream_t st);
-// The same for many contexts at once (a batch's set-up): one Levinson workgroup per job, then
-// the tables of every job.  jobs: device array; max_m: the largest m among them.
-struct GsJob {
-  const double* t_hi;
-  const double* t_lo;
-  double* c;
-  const double2* q;
-  double2* lam_s;
-  double2* lam_c;
-  double* f;
-  float2* lam_s32;
-  float2* lam_c32;
-  float* f32;
-  int m;
-};
-void launch_gs_generator_batched(const GsJob* jobs, int njobs, int max_m, hipStream_t st);
 
 // hat == nullptr: transform u.  Otherwise first u <- 2 u - uprev + hat (stored into uprev),
 // hat in plain rows of pitch ldx

@@ -16,6 +16,7 @@
 
 #include "context.hpp"
 #include "kernels.hpp"
+#include "setup_device.hpp"
 #include "setup_math.hpp"
 
 namespace sadi {
