@@ -98,6 +98,31 @@ def test_batch_run_matches_oracle(path, graph, schedule):
             assert rel(from_dev(u0[k]), ref_prev) < 1e-11, (k, m)
 
 
+def test_batch_members_match_single_contexts():
+    """A batch builds its members' line tables (Levinson recursion, Algorithm 1 tables) for
+    all members in one launch; single contexts build their own.  Both run the same kernel
+    bodies, so each member's run matches the same problem solved on its own context to
+    rounding (the single contexts' tables are pinned to the host's extended-precision
+    tables elsewhere)."""
+    from paper_2312_06206_amd import Solver
+    _say("batch members vs single contexts")
+    b, ms, u0, u1 = make_batch("fft_gs", False, "groups")
+    with b:
+        b.first_step()
+        b.run(9)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for k, m in enumerate(ms):
+            with Solver(m.alpha, m.kappa, m.n, TAU) as s:
+                a = to_dev(m.phi1())
+                c = s.first_step(a, to_dev(0.3 * W.asymmetric_field(m.n, seed=m.n)))
+                s.run(a, c, 9)
+                e = max(rel(from_dev(u1[k]), from_dev(c)), rel(from_dev(u0[k]), from_dev(a)))
+            worst = max(worst, e)
+            assert e < 1e-13, (k, m, e)
+        _say(f"  worst relative difference {worst:.2e}")
+
+
 @pytest.mark.parametrize("counts", [(0, 1, 2), (3, 5), (4, 4)])
 def test_batch_run_lengths_and_graph_replays(counts):
     """Several runs in a row (graph replays with eager work and synchronisation between
