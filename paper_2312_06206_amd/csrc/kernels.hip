@@ -717,14 +717,15 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   const int y = blockIdx.x * Cfg::LPW + L.line;
   const bool live = y < n;
   const int yy = live ? y : 0;
-  double* xo = X + (size_t)yy * ldx;
+  // run steps (US): X in paired rows, as the run's y-sweep reads it
+  double* xo = X + (US ? pair_row(yy, ldx) : (size_t)yy * ldx);
   V d[E];
   rhs_phase<MODE, US>(L, d, smem, S + pair_row(yy, lds_), u + (US ? pair_row(yy, ldu) : (size_t)yy * ldu),
                   MODE == 1 ? phi2 + (size_t)yy * ldu : nullptr, xo, live, sc, tab, root2M, n);
   mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   if (live) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) (xo + T * m)[L.t] = d[m].x;
+    for (int m = 0; m < E; ++m) (xo + ((T * m) << US))[L.t << US] = d[m].x;
   }
 }
 
@@ -884,9 +885,9 @@ __device__ __forceinline__ void cols_gs_fwd_body(const double* __restrict__ X, i
   update_transposed_and_forward<US>(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
 }
 
-// Mixed-precision form of cols_gs_fwd: the y-line solve of column cc of X (plain rows) in
-// float32 with one float64 residual correction (or none), then the same update and next
-// row transform.
+// Mixed-precision form of cols_gs_fwd: the y-line solve of column cc of X (paired rows with US,
+// as the run's x-sweep writes it; plain rows otherwise) in float32 with one float64 residual
+// correction (or none), then the same update and next row transform.
 template <int M, int US>
 __global__ void __launch_bounds__(MixColCfg<M>::NT) SADI_OCC2
 cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __restrict__ ucur,
@@ -904,7 +905,7 @@ cols_gs_fwd_mixed_kernel(const double* __restrict__ X, int ldx, const double* __
   const bool live = col < n;
   const int cc = live ? col : 0;
   V d[E];
-  load_column_pair<M, E, T, 0>(L, d, X, cc, ldx, smem, n);
+  load_column_pair<M, E, T, US>(L, d, X, cc, ldx, smem, n);
   mixed_solve(L, Lf, d, smem, Cfg::keep(smem, L.line), tab, mx);
   update_transposed_and_forward<US>(L, d, smem, ucur, prev_t, n, cc, live, S, lds_, tab, root2M, fwd);
 }

@@ -305,6 +305,8 @@ void launch_adjoint_combine(double ca, double c2, double kappa, int gkind, doubl
 void launch_adjoint_finish(const double* partial, int nrows, double c2, double kappa, double* dkappa,
                            hipStream_t st);
 
+// mixed-precision x-sweep (modes 0 / 1 as launch_rows_rhs_gs).  u_paired (run steps, mode 0):
+// the state in paired rows, and X written in paired rows for launch_cols_gs_fwd_mixed
 template <int M>
 void launch_rows_rhs_mixed(int mode, const double2* S, int lds_, const double* u, int ldu, const double* phi2,
                            double* X, int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab,
@@ -315,8 +317,9 @@ void launch_rows_gs_mixed(double* lines, int ld, int nlines, int n, const FFTTab
 template <int M>
 void launch_cols_gs_mixed(int mode, const double* X, int ldx, const double* ucur, const double* uprev, double* uout,
                           int ldu, int n, const FFTTables<double>& tab, const MixedTables& mx, hipStream_t st);
-// mixed-precision y-line solves of X (plain rows), the update into prev_t's rows and, with fwd,
-// the next step's row transform (as launch_cols_gs_fwd)
+// mixed-precision y-line solves of X, the update into prev_t's rows and, with fwd, the next
+// step's row transform (as launch_cols_gs_fwd).  u_paired: X and both state arrays in paired
+// rows; otherwise all in plain rows
 template <int M>
 void launch_cols_gs_fwd_mixed(const double* X, int ldx, const double* ucur, double* prev_t, int n, double2* S,
                               int lds_, bool fwd, const FFTTables<double>& tab, const MixedTables& mx,

@@ -669,7 +669,7 @@ sadi_status sadi_run(sadi_ctx* c, double* u_prev, double* u_cur, int nsteps) {
     // Three kernels per step: the y-sweep kernel also forms u^{n+1} and the next step's row
     // transform, on the transposed grid (x and y swap roles every step).  u^{n-1} starts in
     // the transposed layout; both arrays are back in the natural layout at the end.  The
-    // float32 line solves take the same schedule (their x-sweep writes X in plain rows).
+    // float32 line solves take the same schedule, X in paired rows as well when the state is.
     auto mark = [&](int k) {
       hipEvent_t e = c->mark(k);
       if (e) (void)hipEventRecord(e, c->stream);
