@@ -714,7 +714,10 @@ rows_rhs_mixed_kernel(const V* __restrict__ S, int lds_, const double* __restric
   __shared__ __align__(16) unsigned char smem[Cfg::LDS_BYTES + Cfg::KEEP_BYTES];
   const L_t L(threadIdx.x);
   const L32 Lf(threadIdx.x);
-  const int y = blockIdx.x * Cfg::LPW + L.line;
+  // at one row per workgroup the two rows of a pair go to one XCD at about the same time
+  // (paired_row_block): they share the L2 lines of S they read and, in runs, of X they write
+  const int blk = Cfg::LPW == 1 ? paired_row_block() : (int)blockIdx.x;
+  const int y = blk * Cfg::LPW + L.line;
   const bool live = y < n;
   const int yy = live ? y : 0;
   // run steps (US): X in paired rows, as the run's y-sweep reads it
@@ -1584,14 +1587,16 @@ void launch_rows_rhs_mixed(int mode, const V* S, int lds_, const double* u, int 
                            int ldx, int n, const StepScalars& sc, const FFTTables<double>& tab, const MixedTables& mx,
                            const V* root2M, hipStream_t st, bool u_paired) {
   const int grid = (n + MixRowCfg<M>::LPW - 1) / MixRowCfg<M>::LPW;
+  // paired_row_block numbers blocks in groups of 16
+  const int grid_p = MixRowCfg<M>::LPW == 1 ? (grid + 15) / 16 * 16 : grid;
   if (mode == 0 && u_paired)
-    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0, 1>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0, 1>), dim3(grid_p), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
                        phi2, X, ldx, n, sc, tab, mx, root2M);
   else if (mode == 0)
-    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0, 0>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 0, 0>), dim3(grid_p), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
                        phi2, X, ldx, n, sc, tab, mx, root2M);
   else
-    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 1, 0>), dim3(grid), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
+    hipLaunchKernelGGL((rows_rhs_mixed_kernel<M, 1, 0>), dim3(grid_p), dim3(MixRowCfg<M>::NT), 0, st, S, lds_, u, ldu,
                        phi2, X, ldx, n, sc, tab, mx, root2M);
 }
 
